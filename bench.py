@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Benchmark of blocked randomized QRCP on one MI355X.
+
+One step = one full factorization A P = Q R (every block: sketch, pivoted QR
+of the sketch, column moves, panel QR, T factor, trailing update) of the
+headline workload: m = n = 8192, FP64, b = 256, p = 10, permutation pivoting,
+A = U diag(s) V^T with Haar U, V and s_j = 10^(-6 (j-1)/8191) (synthetic,
+seeded).  The input is resident in HBM before the timed region; each step
+restores A from a resident copy (a device-to-device copy outside the timed
+events) and factors it.
+
+Prints ONE JSON line (rank 0).  value = normalised GFLOP/s, i.e.
+(2 m n^2 - 2 n^3/3) / time, the Householder-QR flop count (4/3 n^3 for a
+square matrix), which is the metric's normalisation.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GFLOP/s (4/3·n³-normalised) randQRCP n=8192 FP64 vs mixed; bwd/fwd ratio"
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="H1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-blocks", type=int, default=4, help="oracle sample: leading blocks factored on the CPU")
+    return ap.parse_args()
+
+
+def cpu_baseline(A_host, w, nblocks):
+    """The oracle, as it stands, on a bounded sample: the first `nblocks`
+    blocks of the same factorization (rank = nblocks * b)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workloads as W
+    from oracle import rqrcp as O
+    k = min(w.n, nblocks * w.b)
+    t0 = time.perf_counter()
+    O.rqrcp(A_host, w.b, w.p, seed=w.seed, rank=k)
+    dt = time.perf_counter() - t0
+    flops = W.flops_normalised_prefix(w.m, w.n, k)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {nblocks} blocks (rank {k}) of the {w.name} factorization, {dt:.1f} s wall; "
+                      f"normalised by the Householder-QR flops of those {k} columns",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU execution is design-only "
+                                   "(see DESIGN.md), run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1505_08115_amd as R
+    import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    A = W.workload_matrix(w, device=dev)
+    m, n = A.shape
+    A0 = R.colmajor(A)
+    F = torch.empty_like(A0)
+    sizes = R.factor_sizes(m, n, block=w.b, oversample=w.p, pivot=w.pivot, rank=w.rank)
+    jp = torch.empty(n, dtype=torch.int32, device=dev)
+    tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
+    T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
+    S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if w.pivot == "ortho" else None
+    work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
+    info = torch.zeros(4, dtype=torch.int32, device=dev)
+    kw = dict(block=w.b, oversample=w.p, seed=w.seed, pivot=w.pivot, rank=w.rank, info=info)
+
+    for _ in range(args.warmup):
+        F.copy_(A0)
+        R.factor_into(F, jp, tau, T, S, work, **kw)
+    torch.cuda.synchronize()
+    R.timing_enable(True)
+    R.timing_read()
+    times = []
+    for _ in range(args.steps):
+        F.copy_(A0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        R.factor_into(F, jp, tau, T, S, work, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    prof = R.timing_read()
+    R.timing_enable(False)
+    ms = float(np.mean(times))
+    flops = W.flops_normalised(m, n)
+    value = flops / (ms * 1e-3) / 1e9
+
+    # correctness of the timed factorization (independent Q from torch/LAPACK orgqr)
+    Q = torch.linalg.householder_product(F.contiguous(), tau.contiguous())
+    res = float(torch.linalg.norm(A[:, jp.long()] - Q @ torch.triu(F)) / torch.linalg.norm(A)) \
+        if w.pivot == "perm" else None
+    del Q
+
+    # roofline of the dominant kernel: the trailing update C -= (V T^T) W
+    nl, tms, tfl, tby = prof.get("update_gemm", (0, 0.0, 0.0, 0.0))
+    achieved = tfl / (tms * 1e-3) / 1e12 if tms > 0 else 0.0
+    roof = {"kernel": "dgemm C -= (V T^T) W (trailing update)", "bound": "mfma", "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None, "launches_per_step": nl / max(1, args.steps),
+            "avg_launch_ms": tms / max(1, nl), "flops_per_launch": tfl / max(1, nl)}
+    breakdown = {k: {"ms_per_step": v[1] / args.steps, "launches_per_step": v[0] / args.steps,
+                     "tflops": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 and v[2] > 0 else None,
+                     "gbs": (v[3] / (v[1] * 1e-3) / 1e9) if v[1] > 0 and v[3] > 0 else None}
+                 for k, v in prof.items()}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: randomized blocked QRCP, m={m} n={n}, {w.precision}, b={w.b}, "
+                               f"p={w.p}, {w.pivot} pivoting, A = U diag(s) V^T, Haar U,V, seed {w.seed}",
+                   "m": m, "n": n, "block": w.b, "oversample": w.p, "pivot": w.pivot},
+        "roofline": roof,
+        "extra": {"residual": res, "info": info.tolist(), "step_ms": times, "breakdown": breakdown},
+    }
+    if not args.no_cpu_baseline and w.n <= 8192:
+        A_host = A.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(A_host, w, args.cpu_blocks)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

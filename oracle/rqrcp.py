@@ -198,8 +198,9 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
 
     Output keys: F (R on and above the diagonal, Householder vectors below),
     tau, T (list of per-block T), jpvt, S (list of (V_S, tau_S, T_S) per block
-    for ortho), piv (list of per-block swap lists), margins (list), and,
-    with trace=True, Y (list of per-block samples before factoring).
+    for ortho), piv (list of per-block swap lists), margins (list), xnorm
+    (Frobenius norm of each block's trailing matrix X_i), and, with
+    trace=True, Y (list of per-block samples before factoring).
     """
     A = np.array(A, dtype=np.float64, copy=True)
     m, n = A.shape
@@ -210,7 +211,7 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         raise ValueError("rank out of range")
     jpvt = np.arange(n)
     tau = np.zeros(k)
-    out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": []}
+    out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": [], "xnorm": []}
     nblocks = -(-k // b)
     for i in range(nblocks):
         r0 = i * b
@@ -219,6 +220,7 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         X = A[r0:, r0:]
         is_tail = (k == n) and (r0 + b >= n)
         out["blocks"].append((r0, bi))
+        out["xnorm"].append(float(np.linalg.norm(X)))
         if is_tail and tail == "classical" and pivot == "perm":
             # last block of Fig. 3: classical QRCP of the remaining block
             Xc = X.copy()

@@ -1,0 +1,818 @@
+// C ABI of librqrcp: argument checking, workspace planning and the host loop
+// over blocks of the blocked randomized QR (Fig. 3).  Every step runs in the
+// kernels of this library on the handle's stream; the host only computes
+// offsets and enqueues launches, so nothing here waits for the GPU.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "misc.h"
+
+struct rqrcp_timing_rec {
+  int kclass;
+  hipEvent_t start, stop;
+  double flops, bytes;
+};
+
+struct rqrcp_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+  bool timing = false;
+  std::vector<hipEvent_t> free_events;
+  std::vector<hipEvent_t> all_events;
+  std::vector<rqrcp_timing_rec> recs;
+};
+
+namespace rq {
+namespace {
+
+thread_local std::string g_last_error;
+
+rqrcp_status_t fail(rqrcp_handle_t h, rqrcp_status_t st, const std::string &msg) {
+  if (h) h->last_error = msg;
+  g_last_error = msg;
+  return st;
+}
+
+rqrcp_status_t fail_hip(rqrcp_handle_t h, hipError_t e, const char *where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(h, RQRCP_ERR_HIP, m);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Bump {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  }
+};
+
+constexpr int kSlotWords = 512;   // per cooperative launch: barrier state + abort word
+constexpr int kAbortWord = 448;
+
+struct GemmShape {
+  int64_t M, N, K;
+};
+
+size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  GemmF64 g{};
+  g.M = M; g.N = N; g.K = K;
+  const int sp = gemm_f64_splits(g);
+  return sp > 1 ? (size_t)sp * M * N : 0;
+}
+
+struct FactorPlan {
+  int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
+  bool ortho = false, fixed = false, classical_tail = false;
+  int nslots = 0;
+  // byte offsets into the workspace
+  size_t G = 0, Y = 0, YT = 0, Vb = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
+         piv = 0, dest = 0, moved = 0, mcnt = 0, tmp = 0, jtmp = 0, bars = 0, Acopy = 0, total = 0;
+  size_t Y_doubles = 0;
+};
+
+bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
+  return P.classical_tail && i == P.nblocks - 1;
+}
+
+rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, const rqrcp_opts_t *o,
+                         FactorPlan *out) {
+  if (!o) return fail(h, RQRCP_ERR_ARG, "opts is NULL");
+  if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
+  if (n < 1) return fail(h, RQRCP_ERR_ARG, "n must be >= 1");
+  if (m < n) return fail(h, RQRCP_ERR_ARG, "m must be >= n (the method assumes m >= n)");
+  if (o->block < 1) return fail(h, RQRCP_ERR_ARG, "opts.block must be >= 1");
+  if (o->oversample < 0) return fail(h, RQRCP_ERR_ARG, "opts.oversample must be >= 0");
+  if (o->rank < 0 || o->rank > n) return fail(h, RQRCP_ERR_ARG, "opts.rank must be in [0, n]");
+  if (o->pivot != RQRCP_PIVOT_PERM && o->pivot != RQRCP_PIVOT_ORTHO)
+    return fail(h, RQRCP_ERR_ARG, "opts.pivot: unknown value");
+  if (o->precision != RQRCP_PREC_PLAIN && o->precision != RQRCP_PREC_MIXED)
+    return fail(h, RQRCP_ERR_ARG, "opts.precision: unknown value");
+  if (o->precision == RQRCP_PREC_MIXED && dt != RQRCP_F32)
+    return fail(h, RQRCP_ERR_ARG, "opts.precision: MIXED needs F32 storage");
+  if (o->tail != RQRCP_TAIL_CLASSICAL && o->tail != RQRCP_TAIL_SAMPLED)
+    return fail(h, RQRCP_ERR_ARG, "opts.tail: unknown value");
+  if (o->fixed_pivots != 0 && o->fixed_pivots != 1) return fail(h, RQRCP_ERR_ARG, "opts.fixed_pivots must be 0 or 1");
+  if (o->fixed_pivots && o->pivot == RQRCP_PIVOT_ORTHO)
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.fixed_pivots applies to the permutation form only");
+  if (dt == RQRCP_F32) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: F32 storage is not available in this build");
+  FactorPlan P;
+  P.m = m; P.n = n; P.b = o->block; P.p = o->oversample;
+  P.k = o->rank == 0 ? n : o->rank;
+  P.ks = P.b + P.p;
+  P.nblocks = cdiv(P.k, P.b);
+  P.ortho = o->pivot == RQRCP_PIVOT_ORTHO;
+  P.fixed = o->fixed_pivots != 0;
+  P.classical_tail = !P.ortho && !P.fixed && o->tail == RQRCP_TAIL_CLASSICAL && P.k == n;
+  if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
+  if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
+
+  size_t Yd = 0, gpart = 0, ppart = 0;
+  int qnwg = 0;
+  int64_t qk = 1;
+  for (int64_t i = 0; i < P.nblocks; ++i) {
+    const int64_t r0 = i * P.b, bi = std::min(P.b, P.k - r0), mi = m - r0, ni = n - r0;
+    int rpw = 0;
+    const int pn = panel_config(mi, (int)bi, &rpw);
+    if (pn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "panel too large for the panel kernel");
+    ppart = std::max(ppart, panel_part_doubles(pn, (int)bi));
+    if (!P.fixed) {
+      if (block_is_classical_tail(P, i)) {
+        int cpw = 0;
+        const int qn = qrcp_small_config((int)mi, (int)ni, &cpw);
+        if (qn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "last block too large for the pivoted-QR kernel");
+        qnwg = std::max(qnwg, qn);
+        qk = std::max(qk, mi);
+        Yd = std::max(Yd, (size_t)(mi * ni));
+      } else {
+        Yd = std::max(Yd, (size_t)(P.ks * ni));
+        gpart = std::max(gpart, gemm_part_doubles(P.ortho ? bi : P.ks, ni, mi));
+        if (P.ortho) {
+          gpart = std::max(gpart, gemm_part_doubles(m, bi, bi));
+          const int pn2 = panel_config(ni, (int)bi, &rpw);
+          if (pn2 == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "sketch too large for the panel kernel");
+          ppart = std::max(ppart, panel_part_doubles(pn2, (int)bi));
+          gpart = std::max(gpart, gemm_part_doubles(m, bi, ni));
+          gpart = std::max(gpart, gemm_part_doubles(m, ni, bi));
+        } else {
+          int cpw = 0;
+          const int qn = qrcp_small_config((int)P.ks, (int)ni, &cpw);
+          if (qn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "sketch too large for the pivoted-QR kernel");
+          qnwg = std::max(qnwg, qn);
+          qk = std::max(qk, P.ks);
+        }
+      }
+    }
+    gpart = std::max(gpart, gemm_part_doubles(mi, bi, bi));
+    if (ni > bi) {
+      gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, mi));
+      gpart = std::max(gpart, gemm_part_doubles(mi, ni - bi, bi));
+    }
+  }
+  P.Y_doubles = Yd;
+  P.nslots = (int)(3 * P.nblocks + 4);
+  Bump w;
+  const size_t d = sizeof(double);
+  P.G = w.take((o->G || P.fixed) ? 0 : (size_t)P.ks * m * d);
+  P.Y = w.take(Yd * d);
+  P.YT = w.take(P.ortho ? (size_t)n * P.b * d : 0);
+  P.Vb = w.take((size_t)m * P.b * d);
+  P.Vt = w.take((size_t)m * P.b * d);
+  P.Wb = w.take((size_t)P.b * n * d);
+  P.gpart = w.take(gpart * d);
+  P.Sg = w.take((size_t)P.b * P.b * d);
+  P.ppart = w.take(ppart * d);
+  P.pred = w.take((size_t)kPanelW * P.b * d);
+  P.qrec = w.take(qrcp_small_rec_doubles(qnwg) * d);
+  P.qcand = w.take(qrcp_small_cand_doubles(qnwg, (int)qk) * d);
+  P.piv = w.take((size_t)P.b * 4);
+  P.dest = w.take((size_t)n * 4);
+  P.moved = w.take((size_t)2 * P.b * 4);
+  P.mcnt = w.take(4 * 64);
+  P.tmp = w.take(P.ortho || P.fixed ? 0 : (size_t)m * 2 * P.b * d);
+  P.jtmp = w.take((size_t)2 * P.b * 4);
+  P.bars = w.take((size_t)P.nslots * kSlotWords * 4);
+  P.Acopy = w.take(P.fixed ? (size_t)m * n * d : 0);
+  P.total = w.off + 256;
+  *out = P;
+  return RQRCP_OK;
+}
+
+template <typename T>
+T *at(void *base, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+hipEvent_t take_event(rqrcp_handle_t h) {
+  if (h->free_events.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->all_events.push_back(e);
+    return e;
+  }
+  hipEvent_t e = h->free_events.back();
+  h->free_events.pop_back();
+  return e;
+}
+
+// Brackets the launches of one kernel class with events when timing is on.
+struct ScopedTimer {
+  rqrcp_handle_t h;
+  int kclass;
+  double flops, bytes;
+  hipEvent_t start = nullptr;
+  ScopedTimer(rqrcp_handle_t hh, int kc, double f, double b) : h(hh), kclass(kc), flops(f), bytes(b) {
+    if (h->timing) {
+      start = take_event(h);
+      if (start) (void)hipEventRecord(start, h->stream);
+    }
+  }
+  ~ScopedTimer() {
+    if (!start) return;
+    hipEvent_t stop = take_event(h);
+    if (!stop) return;
+    (void)hipEventRecord(stop, h->stream);
+    h->recs.push_back({kclass, start, stop, flops, bytes});
+  }
+};
+
+double qrcp_flops(double k, double ncols, double steps) {
+  double f = 0.0;
+  for (double t = 0; t < steps; t += 1.0) f += 4.0 * (k - t) * (ncols - t);
+  return f;
+}
+
+}  // namespace
+}  // namespace rq
+
+using namespace rq;
+
+extern "C" {
+
+void rqrcp_default_opts(rqrcp_opts_t *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block = 128;
+  o->oversample = 10;
+  o->rank = 0;
+  o->pivot = RQRCP_PIVOT_PERM;
+  o->precision = RQRCP_PREC_PLAIN;
+  o->tail = RQRCP_TAIL_CLASSICAL;
+}
+
+const char *rqrcp_status_string(rqrcp_status_t s) {
+  switch (s) {
+    case RQRCP_OK: return "RQRCP_OK";
+    case RQRCP_ERR_ARG: return "RQRCP_ERR_ARG: invalid argument";
+    case RQRCP_ERR_WORKSPACE: return "RQRCP_ERR_WORKSPACE: workspace missing or too small";
+    case RQRCP_ERR_HIP: return "RQRCP_ERR_HIP: HIP runtime error";
+    case RQRCP_ERR_UNSUPPORTED: return "RQRCP_ERR_UNSUPPORTED: outside the supported range";
+    case RQRCP_ERR_NONFINITE: return "RQRCP_ERR_NONFINITE: non-finite values";
+  }
+  return "unknown status";
+}
+
+const char *rqrcp_last_error(rqrcp_handle_t h) { return h ? h->last_error.c_str() : g_last_error.c_str(); }
+
+rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  *h = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, RQRCP_ERR_UNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+  if (!prop.cooperativeLaunch) return fail(nullptr, RQRCP_ERR_UNSUPPORTED, "device lacks cooperative launch");
+  rqrcp_ctx *c = new rqrcp_ctx();
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->device = dev;
+  *h = c;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_set_stream(rqrcp_handle_t h, void *hip_stream) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
+  if (!h) return RQRCP_OK;
+  for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
+  delete h;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_timing_enable(rqrcp_handle_t h, int enable) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  h->timing = enable != 0;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_timing_read(rqrcp_handle_t h, int kclass, int64_t *launches, double *ms, double *flops,
+                                 double *bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (kclass < 0 || kclass >= RQRCP_K_COUNT) return fail(h, RQRCP_ERR_ARG, "kclass: unknown kernel class");
+  int64_t cnt = 0;
+  double tms = 0.0, tf = 0.0, tb = 0.0;
+  std::vector<rqrcp_timing_rec> keep;
+  for (const auto &r : h->recs) {
+    if (r.kclass != kclass) { keep.push_back(r); continue; }
+    float e = 0.f;
+    hipError_t st = hipEventElapsedTime(&e, r.start, r.stop);
+    if (st != hipSuccess) return fail_hip(h, st, "hipEventElapsedTime (synchronise the stream first)");
+    ++cnt; tms += e; tf += r.flops; tb += r.bytes;
+    h->free_events.push_back(r.start);
+    h->free_events.push_back(r.stop);
+  }
+  h->recs.swap(keep);
+  if (launches) *launches = cnt;
+  if (ms) *ms = tms;
+  if (flops) *flops = tf;
+  if (bytes) *bytes = tb;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_factor_sizes(rqrcp_dtype_t dt, int64_t m, int64_t n, const rqrcp_opts_t *o, size_t *tau_elems,
+                                  size_t *T_elems, size_t *S_elems, size_t *work_bytes) {
+  FactorPlan P;
+  rqrcp_status_t st = make_plan(nullptr, dt, m, n, o, &P);
+  if (st != RQRCP_OK) return st;
+  if (tau_elems) *tau_elems = (size_t)P.k;
+  if (T_elems) *T_elems = (size_t)P.nblocks * P.b * P.b;
+  if (S_elems) {
+    size_t vs = 0;
+    for (int64_t i = 0; i < P.nblocks; ++i) vs += (size_t)(n - i * P.b) * P.b;
+    *S_elems = P.ortho ? vs + (size_t)P.nblocks * P.b + (size_t)P.nblocks * P.b * P.b : 0;
+  }
+  if (work_bytes) *work_bytes = P.total;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_sketch(rqrcp_handle_t h, uint64_t seed, int64_t block, int64_t nsample, int64_t row0,
+                            int64_t nrows, double *G, int64_t ldg) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (!G) return fail(h, RQRCP_ERR_ARG, "G is NULL");
+  if (block < 0 || nsample < 0 || row0 < 0 || nrows < 0) return fail(h, RQRCP_ERR_ARG, "negative size or index");
+  if (ldg < std::max<int64_t>(1, nsample)) return fail(h, RQRCP_ERR_ARG, "ldg < nsample");
+  hipError_t e = launch_sketch(h->stream, seed, block, nsample, row0, nrows, G, ldg);
+  if (e != hipSuccess) return fail_hip(h, e, "sketch");
+  return RQRCP_OK;
+}
+
+#define CHK(call, where)                                  \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return fail_hip(h, e_, where);  \
+  } while (0)
+
+rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av, int64_t lda,
+                            int32_t *jpvt, double *tau, double *T, double *S, const rqrcp_opts_t *o, void *work,
+                            size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  FactorPlan P;
+  rqrcp_status_t st = make_plan(h, dt, m, n, o, &P);
+  if (st != RQRCP_OK) return st;
+  if (!Av) return fail(h, RQRCP_ERR_ARG, "A is NULL");
+  if (lda < m) return fail(h, RQRCP_ERR_ARG, "lda must be >= m");
+  if (!jpvt) return fail(h, RQRCP_ERR_ARG, "jpvt is NULL");
+  if (!tau) return fail(h, RQRCP_ERR_ARG, "tau is NULL");
+  if (!T) return fail(h, RQRCP_ERR_ARG, "T is NULL");
+  if (P.ortho && !S) return fail(h, RQRCP_ERR_ARG, "S is NULL (required for ORTHO)");
+  if (!P.ortho && S) return fail(h, RQRCP_ERR_ARG, "S must be NULL for PERM");
+  if (!work) return fail(h, RQRCP_ERR_WORKSPACE, "work is NULL");
+  if (work_bytes < P.total) return fail(h, RQRCP_ERR_WORKSPACE, "work_bytes smaller than rqrcp_factor_sizes");
+  if (reinterpret_cast<uintptr_t>(work) % 256) return fail(h, RQRCP_ERR_WORKSPACE, "work must be 256-byte aligned");
+
+  hipStream_t s = h->stream;
+  double *A = static_cast<double *>(Av);
+  const int64_t b = P.b, ks = P.ks;
+  double *G = at<double>(work, P.G), *Y = at<double>(work, P.Y), *YT = at<double>(work, P.YT);
+  double *Vb = at<double>(work, P.Vb), *Vt = at<double>(work, P.Vt), *Wb = at<double>(work, P.Wb);
+  double *gpart = at<double>(work, P.gpart), *Sg = at<double>(work, P.Sg);
+  double *ppart = at<double>(work, P.ppart), *pred = at<double>(work, P.pred);
+  double *qrec = at<double>(work, P.qrec), *qcand = at<double>(work, P.qcand);
+  int32_t *piv = at<int32_t>(work, P.piv), *dest = at<int32_t>(work, P.dest);
+  int32_t *moved = at<int32_t>(work, P.moved), *mcnt = at<int32_t>(work, P.mcnt);
+  double *tmp = at<double>(work, P.tmp);
+  int32_t *jtmp = at<int32_t>(work, P.jtmp);
+  unsigned *bars = at<unsigned>(work, P.bars);
+  int32_t *info = o->info;
+
+  // VS blocks, tauS and TS inside S (ortho)
+  std::vector<size_t> vs_off(P.nblocks, 0);
+  size_t vs_total = 0;
+  for (int64_t i = 0; i < P.nblocks; ++i) {
+    vs_off[i] = vs_total;
+    vs_total += (size_t)(n - i * b) * b;
+  }
+  double *tauS = P.ortho ? S + vs_total : nullptr;
+  double *TS = P.ortho ? tauS + P.nblocks * b : nullptr;
+
+  CHK(launch_zero_u32(s, bars, (size_t)P.nslots * kSlotWords), "zero barrier state");
+  CHK(launch_zero_u32(s, T, (size_t)P.nblocks * b * b * 2), "zero T");
+  if (info) CHK(launch_zero_u32(s, info, 4), "zero info");
+  if (P.ortho) CHK(launch_zero_u32(s, S, (vs_total + P.nblocks * b + (size_t)P.nblocks * b * b) * 2), "zero S");
+  if (P.fixed) {
+    double *Ac = at<double>(work, P.Acopy);
+    CHK(launch_copy2d(s, A, lda, Ac, m, m, n), "copy A");
+    CHK(launch_gather_cols(s, Ac, m, m, n, jpvt, n, A, lda), "permute A by jpvt");
+  } else {
+    CHK(launch_iota(s, jpvt, n), "jpvt identity");
+  }
+  int slot = 0;
+  auto next_slot = [&](unsigned **bar, int **ab) {
+    unsigned *base = bars + (size_t)slot * kSlotWords;
+    ++slot;
+    *bar = base;
+    *ab = reinterpret_cast<int *>(base + kAbortWord);
+  };
+  size_t goff = 0;   // offset of the current block's sketch in opts.G
+
+  for (int64_t i = 0; i < P.nblocks; ++i) {
+    const int64_t r0 = i * b, bi = std::min(b, P.k - r0), mi = m - r0, ni = n - r0;
+    double *X = A + r0 + r0 * lda;
+    if (!P.fixed) {
+      if (block_is_classical_tail(P, i)) {
+        // last block of Fig. 3: classical QRCP of the remaining block
+        ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)mi, (double)ni, (double)bi), 16.0 * mi * ni);
+        CHK(launch_copy2d(s, X, lda, Y, mi, mi, ni), "copy last block");
+        CHK(launch_zero_u32(s, mcnt, 1), "zero move count");
+        QrcpSmall q{};
+        q.Y = Y; q.ldy = mi; q.k = (int)mi; q.ncols = (int)ni; q.nsteps = (int)bi;
+        q.piv = piv; q.dest = dest; q.moved = moved; q.moved_cnt = mcnt;
+        q.rec = qrec; q.cand = qcand; q.info = info; q.block_index = (int)i;
+        next_slot(&q.bar, &q.abort_flag);
+        CHK(launch_qrcp_small(s, q), "pivoted QR of the last block");
+        ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
+        CHK(launch_apply_moves(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp), "move columns");
+      } else {
+        const double *Gi;
+        int64_t ldg = ks;
+        if (o->G) {
+          Gi = o->G + goff;
+        } else {
+          ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mi);
+          CHK(launch_sketch(s, o->seed, i, ks, r0, mi, G, ks), "sketch");
+          Gi = G;
+        }
+        goff += (size_t)ks * mi;
+        // Y_i = G_i X_i (Section 4.1, eq. defY).  The orthonormal variant
+        // runs the QR of Y_i^T without pivoting, whose first b_i reflectors
+        // depend only on the first b_i rows of Y_i: only those are formed.
+        const int64_t yrows = P.ortho ? bi : ks;
+        GemmF64 gy{false, false, yrows, ni, mi, Gi, ldg, X, lda, Y, ks, 1.0, 0.0};
+        {
+          ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * yrows * ni * mi, 8.0 * (mi * ni + yrows * mi + yrows * ni));
+          CHK(launch_gemm_f64(s, gy, gpart), "sketch product");
+        }
+        if (!P.ortho) {
+          CHK(launch_zero_u32(s, mcnt, 1), "zero move count");
+          QrcpSmall q{};
+          q.Y = Y; q.ldy = ks; q.k = (int)ks; q.ncols = (int)ni; q.nsteps = (int)bi;
+          q.piv = piv; q.dest = dest; q.moved = moved; q.moved_cnt = mcnt;
+          q.rec = qrec; q.cand = qcand; q.info = info; q.block_index = (int)i;
+          next_slot(&q.bar, &q.abort_flag);
+          {
+            ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)ks, (double)ni, (double)bi), 8.0 * ks * ni);
+            CHK(launch_qrcp_small(s, q), "pivoted QR of the sketch");
+          }
+          ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
+          CHK(launch_apply_moves(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
+              "move columns");
+        } else {
+          // Section 4.2: unpivoted QR of Y_i^T, first b_i steps -> S_i = I - VS TS VS^T
+          double *VS = S + vs_off[i];
+          double *TSi = TS + (size_t)i * b * b;
+          ScopedTimer to(h, RQRCP_K_ORTHO, 2.0 * ni * bi * bi + 4.0 * m * ni * bi + 2.0 * m * bi * bi,
+                         8.0 * (3.0 * m * ni + 3.0 * ni * bi));
+          CHK(launch_transpose(s, Y, ks, YT, ni, bi, ni), "transpose sketch");
+          PanelQR pq{};
+          pq.P = YT; pq.ldp = ni; pq.mi = ni; pq.nb = (int)bi;
+          pq.tau = tauS + i * b; pq.V = VS; pq.ldv = ni; pq.S = Sg;
+          pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i;
+          next_slot(&pq.bar, &pq.abort_flag);
+          CHK(launch_panel_qr(s, pq), "QR of the sketch");
+          CHK(launch_wy_t(s, (int)bi, tauS + i * b, Sg, TSi, b), "T of the sketch reflectors");
+          // A(0:m, r0:n) <- A(0:m, r0:n) (I - VS TS VS^T), all m rows
+          double *Ac = A + r0 * lda;
+          GemmF64 g1{false, false, m, bi, ni, Ac, lda, VS, ni, Vb, m, 1.0, 0.0};
+          CHK(launch_gemm_f64(s, g1, gpart), "A VS");
+          GemmF64 g2{false, false, m, bi, bi, Vb, m, TSi, b, Vt, m, 1.0, 0.0};
+          CHK(launch_gemm_f64(s, g2, gpart), "(A VS) TS");
+          GemmF64 g3{false, true, m, ni, bi, Vt, m, VS, ni, Ac, lda, -1.0, 1.0};
+          CHK(launch_gemm_f64(s, g3, gpart), "A -= (A VS TS) VS^T");
+        }
+      }
+    }
+    // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi)
+    PanelQR pq{};
+    pq.P = X; pq.ldp = lda; pq.mi = mi; pq.nb = (int)bi;
+    pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+    pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i;
+    next_slot(&pq.bar, &pq.abort_flag);
+    {
+      ScopedTimer tp(h, RQRCP_K_PANEL, 2.0 * mi * bi * bi - 2.0 * bi * bi * bi / 3.0, 24.0 * mi * bi);
+      CHK(launch_panel_qr(s, pq), "panel QR");
+    }
+    double *Ti = T + (size_t)i * b * b;
+    {
+      ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
+      CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
+    }
+    if (ni > bi) {
+      // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1)
+      double *C = X + bi * lda;
+      const double nc = (double)(ni - bi);
+      GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
+      {
+        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
+        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
+      }
+      GemmF64 gw{true, false, bi, ni - bi, mi, Vb, mi, C, lda, Wb, bi, 1.0, 0.0};
+      {
+        ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi, 8.0 * (mi * nc + mi * bi + bi * nc));
+        CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
+      }
+      GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0};
+      {
+        ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi, 8.0 * (2.0 * mi * nc + mi * bi + bi * nc));
+        CHK(launch_gemm_f64(s, gu, gpart), "C -= (V T^T) W");
+      }
+    }
+  }
+  (void)piv;
+  return RQRCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Q, P, truncation and the backward pass
+
+size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t, int64_t m, int64_t k, int64_t b, int64_t ncol) {
+  if (m < 1 || k < 1 || b < 1 || ncol < 0) return 0;
+  size_t gp = 0;
+  for (int64_t r0 = 0; r0 < k; r0 += b) {
+    const int64_t bi = std::min(b, k - r0), mi = m - r0;
+    gp = std::max(gp, gemm_part_doubles(bi, ncol, mi));
+    gp = std::max(gp, gemm_part_doubles(bi, ncol, bi));
+    gp = std::max(gp, gemm_part_doubles(mi, ncol, bi));
+  }
+  Bump w;
+  w.take((size_t)m * b * 8);
+  w.take((size_t)b * ncol * 8);
+  w.take((size_t)b * ncol * 8);
+  w.take(gp * 8);
+  return w.off + 256;
+}
+
+static rqrcp_status_t apply_q_impl(rqrcp_handle_t h, int trans, int64_t m, int64_t k, int64_t b, const double *VR,
+                                   int64_t ldvr, const double *T, int64_t ncol, double *C, int64_t ldc, void *work) {
+  hipStream_t s = h->stream;
+  Bump w;
+  double *Vb = at<double>(work, w.take((size_t)m * b * 8));
+  double *W1 = at<double>(work, w.take((size_t)b * ncol * 8));
+  double *W2 = at<double>(work, w.take((size_t)b * ncol * 8));
+  size_t gp = 0;
+  for (int64_t r0 = 0; r0 < k; r0 += b) {
+    const int64_t bi = std::min(b, k - r0), mi = m - r0;
+    gp = std::max(gp, gemm_part_doubles(bi, ncol, mi));
+    gp = std::max(gp, gemm_part_doubles(bi, ncol, bi));
+    gp = std::max(gp, gemm_part_doubles(mi, ncol, bi));
+  }
+  double *part = at<double>(work, w.take(gp * 8));
+  const int64_t nb = cdiv(k, b);
+  for (int64_t t = 0; t < nb; ++t) {
+    const int64_t i = trans ? t : nb - 1 - t;
+    const int64_t r0 = i * b, bi = std::min(b, k - r0), mi = m - r0;
+    const double *Ti = T + (size_t)i * b * b;
+    CHK(launch_extract_v(s, VR + r0 + r0 * ldvr, ldvr, mi, bi, Vb, mi), "extract V");
+    double *Cs = C + r0;
+    GemmF64 g1{true, false, bi, ncol, mi, Vb, mi, Cs, ldc, W1, bi, 1.0, 0.0};
+    CHK(launch_gemm_f64(s, g1, part), "V^T C");
+    // Q_i^T C = C - V T^T V^T C ; Q_i C = C - V T V^T C
+    GemmF64 g2{trans ? true : false, false, bi, ncol, bi, Ti, b, W1, bi, W2, bi, 1.0, 0.0};
+    CHK(launch_gemm_f64(s, g2, part), "T W");
+    GemmF64 g3{false, false, mi, ncol, bi, Vb, mi, W2, bi, Cs, ldc, -1.0, 1.0};
+    CHK(launch_gemm_f64(s, g3, part), "C -= V (T W)");
+  }
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t m, int64_t k, int64_t b,
+                             const void *VR, int64_t ldvr, const double *T, int64_t ncol, void *C, int64_t ldc,
+                             void *work, size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
+  if (m < 1 || k < 1 || k > m || b < 1) return fail(h, RQRCP_ERR_ARG, "need 1 <= k <= m and b >= 1");
+  if (!VR || !T || !C) return fail(h, RQRCP_ERR_ARG, "VR, T and C must not be NULL");
+  if (ldvr < m || ldc < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldc must be >= m");
+  if (ncol < 0) return fail(h, RQRCP_ERR_ARG, "ncol must be >= 0");
+  if (ncol == 0) return RQRCP_OK;
+  if (!work || work_bytes < rqrcp_apply_q_work_bytes(dt, m, k, b, ncol))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_q_work_bytes");
+  return apply_q_impl(h, trans, m, k, b, static_cast<const double *>(VR), ldvr, T, ncol, static_cast<double *>(C), ldc,
+                      work);
+}
+
+size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t, int64_t nrow, int64_t n, int64_t k, int64_t b) {
+  if (nrow < 0 || n < 1 || b < 1) return 0;
+  size_t gp = 0;
+  for (int64_t r0 = 0; r0 < k; r0 += b) {
+    const int64_t bi = std::min(b, k - r0), ni = n - r0;
+    gp = std::max(gp, gemm_part_doubles(nrow, bi, ni));
+    gp = std::max(gp, gemm_part_doubles(nrow, bi, bi));
+    gp = std::max(gp, gemm_part_doubles(nrow, ni, bi));
+  }
+  Bump w;
+  w.take((size_t)nrow * n * 8);
+  w.take((size_t)nrow * b * 8);
+  w.take((size_t)nrow * b * 8);
+  w.take(gp * 8);
+  return w.off + 256;
+}
+
+static rqrcp_status_t apply_p_impl(rqrcp_handle_t h, int trans, int64_t nrow, int64_t n, int64_t k, int64_t b,
+                                   const int32_t *jpvt, const double *S, double *C, int64_t ldc, void *work) {
+  hipStream_t s = h->stream;
+  Bump w;
+  double *tmpc = at<double>(work, w.take((size_t)nrow * n * 8));
+  double *Z1 = at<double>(work, w.take((size_t)nrow * b * 8));
+  double *Z2 = at<double>(work, w.take((size_t)nrow * b * 8));
+  size_t gp = 0;
+  for (int64_t r0 = 0; r0 < k; r0 += b) {
+    const int64_t bi = std::min(b, k - r0), ni = n - r0;
+    gp = std::max(gp, gemm_part_doubles(nrow, bi, ni));
+    gp = std::max(gp, gemm_part_doubles(nrow, bi, bi));
+    gp = std::max(gp, gemm_part_doubles(nrow, ni, bi));
+  }
+  double *part = at<double>(work, w.take(gp * 8));
+  if (!S) {
+    CHK(launch_copy2d(s, C, ldc, tmpc, nrow, nrow, n), "copy C");
+    if (!trans) CHK(launch_gather_cols(s, tmpc, nrow, nrow, n, jpvt, n, C, ldc), "C P");
+    else CHK(launch_scatter_cols(s, tmpc, nrow, nrow, jpvt, n, C, ldc, n, false), "C P^T");
+    return RQRCP_OK;
+  }
+  const int64_t nb = cdiv(k, b);
+  std::vector<size_t> vs_off(nb);
+  size_t vs_total = 0;
+  for (int64_t i = 0; i < nb; ++i) { vs_off[i] = vs_total; vs_total += (size_t)(n - i * b) * b; }
+  const double *TS = S + vs_total + nb * b;
+  for (int64_t t = 0; t < nb; ++t) {
+    const int64_t i = trans ? nb - 1 - t : t;
+    const int64_t r0 = i * b, bi = std::min(b, k - r0), ni = n - r0;
+    const double *VS = S + vs_off[i];
+    const double *TSi = TS + (size_t)i * b * b;
+    double *Cc = C + r0 * ldc;
+    GemmF64 g1{false, false, nrow, bi, ni, Cc, ldc, VS, ni, Z1, nrow, 1.0, 0.0};
+    CHK(launch_gemm_f64(s, g1, part), "C VS");
+    GemmF64 g2{false, trans ? true : false, nrow, bi, bi, Z1, nrow, TSi, b, Z2, nrow, 1.0, 0.0};
+    CHK(launch_gemm_f64(s, g2, part), "(C VS) TS");
+    GemmF64 g3{false, true, nrow, ni, bi, Z2, nrow, VS, ni, Cc, ldc, -1.0, 1.0};
+    CHK(launch_gemm_f64(s, g3, part), "C -= (..) VS^T");
+  }
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t nrow, int64_t n, int64_t k,
+                             int64_t b, const int32_t *jpvt, const double *S, void *C, int64_t ldc, void *work,
+                             size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
+  if (nrow < 0 || n < 1 || b < 1 || k < 1 || k > n) return fail(h, RQRCP_ERR_ARG, "need nrow >= 0, 1 <= k <= n, b >= 1");
+  if (!C || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "C and one of jpvt / S must be given");
+  if (ldc < std::max<int64_t>(1, nrow)) return fail(h, RQRCP_ERR_ARG, "ldc must be >= nrow");
+  if (nrow == 0) return RQRCP_OK;
+  if (!work || work_bytes < rqrcp_apply_p_work_bytes(dt, nrow, n, k, b))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_p_work_bytes");
+  return apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, static_cast<double *>(C), ldc, work);
+}
+
+size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+  if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
+  Bump w;
+  w.take((size_t)m * k * 8);                               // Q_k
+  w.take((size_t)k * n * 8);                               // R_k P^T
+  w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k), rqrcp_apply_p_work_bytes(dt, k, n, k, b)));
+  w.take(gemm_part_doubles(m, n, k) * 8);
+  return w.off + 256;
+}
+
+static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t b, const double *VR, int64_t ldvr,
+                              const double *T, double *Qk, void *work) {
+  CHK(launch_set_identity(h->stream, Qk, m, m, k), "identity");
+  return apply_q_impl(h, 0, m, k, b, VR, ldvr, T, k, Qk, m, work);
+}
+
+rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
+                             const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T, const double *S,
+                             void *Ak, int64_t ldak, void *work, size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (!VR || !T || !Ak || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "VR, T, Ak and jpvt (or S) are required");
+  if (ldvr < m || ldak < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldak must be >= m");
+  if (!work || work_bytes < rqrcp_lowrank_work_bytes(dt, m, n, k, b))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_work_bytes");
+  hipStream_t s = h->stream;
+  const double *F = static_cast<const double *>(VR);
+  Bump w;
+  double *Qk = at<double>(work, w.take((size_t)m * k * 8));
+  double *RP = at<double>(work, w.take((size_t)k * n * 8));
+  void *sub = at<void>(work, w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k),
+                                             rqrcp_apply_p_work_bytes(dt, k, n, k, b))));
+  double *part = at<double>(work, w.take(gemm_part_doubles(m, n, k) * 8));
+  // R_k P^* (k x n)
+  CHK(launch_extract_r(s, F, ldvr, k, n, RP, k), "extract R_k");
+  rqrcp_status_t st = apply_p_impl(h, 1, k, n, k, b, jpvt, S, RP, k, sub);
+  if (st != RQRCP_OK) return st;
+  st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
+  if (st != RQRCP_OK) return st;
+  GemmF64 g{false, false, m, n, k, Qk, m, RP, k, static_cast<double *>(Ak), ldak, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g, part), "Q_k (R_k P^*)");
+  return RQRCP_OK;
+}
+
+size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+  if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
+  Bump w;
+  w.take((size_t)m * k * 8);   // Q_k
+  w.take((size_t)k * n * 8);   // R_k
+  w.take((size_t)n * k * 8);   // P R_k^T, then Gbar^T Q_k
+  w.take((size_t)m * k * 8);   // M
+  w.take((size_t)k * k * 8);   // Q_k^T M
+  w.take((size_t)k * k * 8);   // R_11^{-1}
+  w.take((size_t)m * k * 8);   // Z
+  w.take((size_t)k * n * 8);   // Q_k^T Gbar
+  w.take(rqrcp_apply_q_work_bytes(dt, m, k, b, k));
+  size_t gp = 0;
+  gp = std::max(gp, gemm_part_doubles(m, k, n));
+  gp = std::max(gp, gemm_part_doubles(n, k, m));
+  gp = std::max(gp, gemm_part_doubles(k, k, m));
+  gp = std::max(gp, gemm_part_doubles(m, k, k));
+  gp = std::max(gp, gemm_part_doubles(k, n, m));
+  gp = std::max(gp, gemm_part_doubles(m, n, k));
+  w.take(gp * 8);
+  return w.off + 256;
+}
+
+rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
+                                      const void *Av, int64_t lda, const void *VR, int64_t ldvr, const int32_t *jpvt,
+                                      const double *T, const void *dAkv, int64_t ldg, void *dAv, int64_t ldda,
+                                      void *work, size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (!Av || !VR || !jpvt || !T || !dAkv || !dAv) return fail(h, RQRCP_ERR_ARG, "a required pointer is NULL");
+  if (lda < m || ldvr < m || ldg < m || ldda < m) return fail(h, RQRCP_ERR_ARG, "leading dimensions must be >= m");
+  if (!work || work_bytes < rqrcp_lowrank_backward_work_bytes(dt, m, n, k, b))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_backward_work_bytes");
+  hipStream_t s = h->stream;
+  const double *A = static_cast<const double *>(Av);
+  const double *F = static_cast<const double *>(VR);
+  const double *Gb = static_cast<const double *>(dAkv);
+  double *dA = static_cast<double *>(dAv);
+  Bump w;
+  double *Qk = at<double>(work, w.take((size_t)m * k * 8));
+  double *Rk = at<double>(work, w.take((size_t)k * n * 8));
+  double *NK = at<double>(work, w.take((size_t)n * k * 8));
+  double *M = at<double>(work, w.take((size_t)m * k * 8));
+  double *KK = at<double>(work, w.take((size_t)k * k * 8));
+  double *Ri = at<double>(work, w.take((size_t)k * k * 8));
+  double *Z = at<double>(work, w.take((size_t)m * k * 8));
+  double *KN = at<double>(work, w.take((size_t)k * n * 8));
+  void *sub = at<void>(work, w.take(rqrcp_apply_q_work_bytes(dt, m, k, b, k)));
+  size_t gp = 0;
+  gp = std::max(gp, gemm_part_doubles(m, k, n));
+  gp = std::max(gp, gemm_part_doubles(n, k, m));
+  gp = std::max(gp, gemm_part_doubles(k, k, m));
+  gp = std::max(gp, gemm_part_doubles(m, k, k));
+  gp = std::max(gp, gemm_part_doubles(k, n, m));
+  gp = std::max(gp, gemm_part_doubles(m, n, k));
+  double *part = at<double>(work, w.take(gp * 8));
+
+  rqrcp_status_t st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
+  if (st != RQRCP_OK) return st;
+  CHK(launch_extract_r(s, F, ldvr, k, n, Rk, k), "extract R_k");
+  // P R_k^T (n x k): row jpvt[j] is column j of R_k
+  CHK(launch_scatter_rows_t(s, Rk, k, k, jpvt, n, NK, n), "P R_k^T");
+  // M = Gbar (P R_k^T)
+  GemmF64 g1{false, false, m, k, n, Gb, ldg, NK, n, M, m, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g1, part), "Gbar P R_k^T");
+  // M += A (Gbar^T Q_k)
+  GemmF64 g2{true, false, n, k, m, Gb, ldg, Qk, m, NK, n, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g2, part), "Gbar^T Q_k");
+  GemmF64 g3{false, false, m, k, n, A, lda, NK, n, M, m, 1.0, 1.0};
+  CHK(launch_gemm_f64(s, g3, part), "A (Gbar^T Q_k)");
+  // M <- (I - Q_k Q_k^T) M
+  GemmF64 g4{true, false, k, k, m, Qk, m, M, m, KK, k, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g4, part), "Q_k^T M");
+  GemmF64 g5{false, false, m, k, k, Qk, m, KK, k, M, m, -1.0, 1.0};
+  CHK(launch_gemm_f64(s, g5, part), "M -= Q_k (Q_k^T M)");
+  // Z = M R_11^{-T}
+  CHK(launch_tri_inv_upper(s, Rk, k, k, Ri, k), "R_11^{-1}");
+  GemmF64 g6{false, true, m, k, k, M, m, Ri, k, Z, m, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g6, part), "M R_11^{-T}");
+  // dA = Q_k (Q_k^T Gbar), then dA(:, jpvt[0:k]) += Z
+  GemmF64 g7{true, false, k, n, m, Qk, m, Gb, ldg, KN, k, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g7, part), "Q_k^T Gbar");
+  GemmF64 g8{false, false, m, n, k, Qk, m, KN, k, dA, ldda, 1.0, 0.0};
+  CHK(launch_gemm_f64(s, g8, part), "Q_k (Q_k^T Gbar)");
+  CHK(launch_scatter_cols(s, Z, m, m, jpvt, k, dA, ldda, n, true), "scatter Z");
+  return RQRCP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal declarations shared by the HIP sources of librqrcp (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rqrcp.h"
+
+namespace rq {
+
+// ---------------------------------------------------------------------------
+// Device helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Grid-wide barrier for cooperatively launched kernels.  Workgroups arrive on
+// one of 8 group counters (grouped by blockIdx % 8, i.e. by the XCD that the
+// round-robin dispatcher puts them on); the last arrival of a group arrives
+// on the top counter, and the last top arrival publishes the new generation.
+// Counters only grow, so no reset is needed between barriers; the host zeroes
+// the state once before the launch.  Every wait is bounded: after `kSpinLimit`
+// polls the waiter raises the abort word and every later wait returns at once,
+// so that a broken launch drains instead of hanging.
+struct GridBarrier {
+  unsigned *state;   // [0]: generation, [32]: top counter, [64 + 32 g]: group g
+  int *abort_flag;   // shared abort word (zeroed by the host)
+};
+
+constexpr long kSpinLimit = 1L << 25;
+
+__device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen) {
+  __threadfence();
+  __syncthreads();
+  __shared__ int s_abort;
+  if (threadIdx.x == 0) {
+    const unsigned nwg = gridDim.x;
+    const unsigned ngroups = nwg < 8 ? nwg : 8;
+    const unsigned g = blockIdx.x % ngroups;
+    const unsigned gsize = (nwg - g + ngroups - 1) / ngroups;
+    unsigned *gen_p = gb.state;
+    unsigned *top_p = gb.state + 32;
+    unsigned *grp_p = gb.state + 64 + 32 * g;
+    const unsigned target = gen + 1;
+    unsigned old = __hip_atomic_fetch_add(grp_p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == gsize * target) {
+      unsigned t = __hip_atomic_fetch_add(top_p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (t + 1 == ngroups * target)
+        __hip_atomic_store(gen_p, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ab = 0;
+    long spins = 0;
+    while (__hip_atomic_load(gen_p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_abort = ab;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  gen += 1;
+  return s_abort == 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (implemented in the .hip files)
+
+// Gaussian sketch: G(r, g - row0) for r < nsample, g in [row0, row0 + nrows).
+hipError_t launch_sketch(hipStream_t s, uint64_t seed, int64_t block, int64_t nsample, int64_t row0,
+                         int64_t nrows, double *G, int64_t ldg);
+
+// C = alpha op(A) op(B) + beta C in FP64 (MFMA), column-major.  When the
+// problem is split along K the partial products go to `partial` (at least
+// splits * M * N doubles) and a fixed-order reduction produces C.
+struct GemmF64 {
+  bool ta, tb;
+  int64_t M, N, K;
+  const double *A; int64_t lda;
+  const double *B; int64_t ldb;
+  double *C; int64_t ldc;
+  double alpha, beta;
+};
+int gemm_f64_splits(const GemmF64 &g);          // split count the launcher will use
+hipError_t launch_gemm_f64(hipStream_t s, const GemmF64 &g, double *partial);
+
+// Zero-fill of n 32-bit words (safe inside graph capture, unlike memset nodes).
+hipError_t launch_zero_u32(hipStream_t s, void *p, size_t nwords);
+
+// Cooperative pivoted QR of a small k x ncols matrix, first nsteps steps
+// (classical pivot rule; only the pivot decisions are produced).
+struct QrcpSmall {
+  double *Y; int64_t ldy; int k; int ncols; int nsteps;
+  int32_t *piv;          // [nsteps] swap partner of position j
+  int32_t *dest;         // [ncols] final position of each column
+  int32_t *moved;        // [2*nsteps] columns whose position changed
+  int32_t *moved_cnt;    // [1]
+  double *rec;           // exchange records, qrcp_small_rec_doubles()
+  double *cand;          // exchange columns, qrcp_small_cand_doubles()
+  unsigned *bar;         // barrier state (zeroed), kBarrierWords words
+  int *abort_flag;       // zeroed
+  int32_t *info;         // may be NULL
+  int block_index;
+};
+constexpr int kBarrierWords = 64 + 32 * 8;
+int qrcp_small_config(int k, int ncols, int *cpw);   // returns workgroups (0 = unsupported)
+size_t qrcp_small_rec_doubles(int nwg);
+size_t qrcp_small_cand_doubles(int nwg, int k);
+hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q);
+
+// Move the columns listed by a QrcpSmall run: column r0 + c goes to r0 +
+// dest[c], for all m rows of A and for jpvt.
+hipError_t launch_apply_moves(hipStream_t s, double *A, int64_t lda, int64_t m, int64_t r0,
+                              const int32_t *moved, const int32_t *moved_cnt, const int32_t *dest,
+                              int max_moved, double *tmp, int32_t *jpvt, int32_t *jtmp);
+
+// Cooperative unpivoted Householder QR of an mi x nb panel (FP64).
+struct PanelQR {
+  double *P; int64_t ldp; int64_t mi; int nb;
+  double *tau;            // [nb]
+  double *V; int64_t ldv; // explicit unit-lower V (mi x nb)
+  double *S;              // nb x nb Gram V^T V (column j valid for rows <= j)
+  double *part;           // partial sums, panel_part_doubles()
+  double *red;            // reduced sums, nb * kPanelW doubles
+  unsigned *bar;
+  int *abort_flag;
+  int32_t *info;
+  int block_index;
+};
+constexpr int kPanelW = 32;
+int panel_config(int64_t mi, int nb, int *rpw);   // workgroups (0 = unsupported)
+size_t panel_part_doubles(int nwg, int nb);
+hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p);
+
+// T of the compact WY form from tau and the Gram matrix S = V^T V.
+hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt);
+
+}  // namespace rq

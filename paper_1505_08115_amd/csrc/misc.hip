@@ -1,0 +1,161 @@
+// Small data-movement kernels around the factorization: copies, transposes,
+// extraction of the explicit Householder vectors V and of R from the factored
+// matrix, column gathers/scatters for the permutation P, and the inverse of
+// an upper-triangular block.  All are bandwidth-bound element maps with
+// coalesced accesses along the column-major leading dimension.
+#include "common.h"
+#include "misc.h"
+
+namespace rq {
+
+namespace {
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 16384) g = 16384;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void copy2d_kernel(const double *__restrict__ s, int64_t lds, double *__restrict__ d, int64_t ldd,
+                              int64_t rows, int64_t cols) {
+  GRID_STRIDE(i, rows * cols) {
+    const int64_t r = i % rows, c = i / rows;
+    d[r + c * ldd] = s[r + c * lds];
+  }
+}
+
+__global__ void transpose_kernel(const double *__restrict__ s, int64_t lds, double *__restrict__ d, int64_t ldd,
+                                 int64_t rows, int64_t cols) {
+  // d (cols x rows) = s^T; reads coalesced along rows of s
+  GRID_STRIDE(i, rows * cols) {
+    const int64_t r = i % rows, c = i / rows;
+    d[c + r * ldd] = s[r + c * lds];
+  }
+}
+
+__global__ void extract_v_kernel(const double *__restrict__ F, int64_t ldf, int64_t mi, int64_t bi,
+                                 double *__restrict__ V, int64_t ldv) {
+  GRID_STRIDE(i, mi * bi) {
+    const int64_t r = i % mi, c = i / mi;
+    V[r + c * ldv] = r > c ? F[r + c * ldf] : (r == c ? 1.0 : 0.0);
+  }
+}
+
+__global__ void extract_r_kernel(const double *__restrict__ F, int64_t ldf, int64_t k, int64_t n,
+                                 double *__restrict__ R, int64_t ldr) {
+  GRID_STRIDE(i, k * n) {
+    const int64_t r = i % k, c = i / k;
+    R[r + c * ldr] = r <= c ? F[r + c * ldf] : 0.0;
+  }
+}
+
+__global__ void gather_cols_kernel(const double *__restrict__ s, int64_t lds, int64_t rows, int64_t scols,
+                                   const int32_t *__restrict__ idx, int64_t ncols, double *__restrict__ d,
+                                   int64_t ldd) {
+  GRID_STRIDE(i, rows * ncols) {
+    const int64_t r = i % rows, c = i / rows;
+    const int64_t src = idx[c];
+    // an index outside the source (not a permutation) yields NaN, never a stray read
+    d[r + c * ldd] = (src >= 0 && src < scols) ? s[r + src * lds] : __builtin_nan("");
+  }
+}
+
+__global__ void scatter_cols_kernel(const double *__restrict__ s, int64_t lds, int64_t rows, const int32_t *__restrict__ idx,
+                                    int64_t ncols, double *__restrict__ d, int64_t ldd, int64_t dcols, int add) {
+  GRID_STRIDE(i, rows * ncols) {
+    const int64_t r = i % rows, c = i / rows;
+    const int64_t dc = idx[c];
+    if (dc < 0 || dc >= dcols) continue;
+    double *p = d + r + dc * ldd;
+    *p = add ? *p + s[r + c * lds] : s[r + c * lds];
+  }
+}
+
+__global__ void scatter_rows_t_kernel(const double *__restrict__ s, int64_t lds, int64_t k, const int32_t *__restrict__ idx,
+                                      int64_t ncols, double *__restrict__ d, int64_t ldd) {
+  // d(idx[j], c) = s(c, j) for c < k, j < ncols
+  GRID_STRIDE(i, k * ncols) {
+    const int64_t c = i % k, j = i / k;
+    const int64_t dr = idx[j];
+    if (dr < 0 || dr >= ncols) continue;
+    d[dr + c * ldd] = s[c + j * lds];
+  }
+}
+
+__global__ void set_identity_kernel(double *__restrict__ E, int64_t lde, int64_t rows, int64_t cols) {
+  GRID_STRIDE(i, rows * cols) {
+    const int64_t r = i % rows, c = i / rows;
+    E[r + c * lde] = r == c ? 1.0 : 0.0;
+  }
+}
+
+__global__ void iota_kernel(int32_t *__restrict__ p, int64_t n) {
+  GRID_STRIDE(i, n) p[i] = (int32_t)i;
+}
+
+// Rinv = R^{-1} for an upper-triangular k x k R: column j solves R x = e_j by
+// back substitution (one thread per column).
+__global__ void tri_inv_upper_kernel(const double *__restrict__ R, int64_t ldr, int64_t k, double *__restrict__ Ri,
+                                     int64_t ldi) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double *x = Ri + j * ldi;
+  for (int64_t i = k - 1; i > j; --i) x[i] = 0.0;
+  for (int64_t i = j; i >= 0; --i) {
+    double acc = (i == j) ? 1.0 : 0.0;
+    for (int64_t q = i + 1; q <= j; ++q) acc -= R[i + q * ldr] * x[q];
+    x[i] = acc / R[i + i * ldr];
+  }
+}
+
+}  // namespace
+
+#define LAUNCH1D(kern, n, ...)                                                         \
+  do {                                                                                 \
+    if ((n) <= 0) return hipSuccess;                                                   \
+    hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(256), 0, s, __VA_ARGS__);         \
+    return hipGetLastError();                                                          \
+  } while (0)
+
+hipError_t launch_copy2d(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                         int64_t cols) {
+  LAUNCH1D(copy2d_kernel, rows * cols, src, lds, dst, ldd, rows, cols);
+}
+hipError_t launch_transpose(hipStream_t s, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                            int64_t cols) {
+  LAUNCH1D(transpose_kernel, rows * cols, src, lds, dst, ldd, rows, cols);
+}
+hipError_t launch_extract_v(hipStream_t s, const double *F, int64_t ldf, int64_t mi, int64_t bi, double *V,
+                            int64_t ldv) {
+  LAUNCH1D(extract_v_kernel, mi * bi, F, ldf, mi, bi, V, ldv);
+}
+hipError_t launch_extract_r(hipStream_t s, const double *F, int64_t ldf, int64_t k, int64_t n, double *R,
+                            int64_t ldr) {
+  LAUNCH1D(extract_r_kernel, k * n, F, ldf, k, n, R, ldr);
+}
+hipError_t launch_gather_cols(hipStream_t s, const double *src, int64_t lds, int64_t rows, int64_t scols,
+                              const int32_t *idx, int64_t ncols, double *dst, int64_t ldd) {
+  LAUNCH1D(gather_cols_kernel, rows * ncols, src, lds, rows, scols, idx, ncols, dst, ldd);
+}
+hipError_t launch_scatter_cols(hipStream_t s, const double *src, int64_t lds, int64_t rows, const int32_t *idx,
+                               int64_t ncols, double *dst, int64_t ldd, int64_t dcols, bool add) {
+  LAUNCH1D(scatter_cols_kernel, rows * ncols, src, lds, rows, idx, ncols, dst, ldd, dcols, add ? 1 : 0);
+}
+hipError_t launch_scatter_rows_t(hipStream_t s, const double *src, int64_t lds, int64_t k, const int32_t *idx,
+                                 int64_t ncols, double *dst, int64_t ldd) {
+  LAUNCH1D(scatter_rows_t_kernel, k * ncols, src, lds, k, idx, ncols, dst, ldd);
+}
+hipError_t launch_set_identity(hipStream_t s, double *E, int64_t lde, int64_t rows, int64_t cols) {
+  LAUNCH1D(set_identity_kernel, rows * cols, E, lde, rows, cols);
+}
+hipError_t launch_iota(hipStream_t s, int32_t *p, int64_t n) { LAUNCH1D(iota_kernel, n, p, n); }
+hipError_t launch_tri_inv_upper(hipStream_t s, const double *R, int64_t ldr, int64_t k, double *Ri, int64_t ldi) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s, R, ldr, k, Ri, ldi);
+  return hipGetLastError();
+}
+
+}  // namespace rq

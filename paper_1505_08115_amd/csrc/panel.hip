@@ -1,0 +1,309 @@
+// Unpivoted Householder QR of the m' x b panel (Fig. 3, the panel step with
+// P-hat = I; Sections 3.1-3.2) and the T factor of its compact WY form
+// (Section 5.1: H_1 ... H_b = I - V T V^T).
+//
+// One persistent cooperative launch per panel.  Panel rows are dealt in
+// contiguous ranges of rpw rows to workgroups; a workgroup only ever touches
+// its own rows, so all cross-workgroup traffic is the reductions.  Columns
+// are processed in slabs of kPanelW that live in LDS:
+//   * column step j: every workgroup forms partial sums over its rows of
+//     g_c = x_j^T x_c (rows >= j) and contributes x_c(j) (owner only), for the
+//     remaining slab columns c >= j; one grid barrier; every workgroup sums
+//     the partials in the same fixed order.  With alpha = x_j(j),
+//     beta = -sign(alpha) |x_j|, tau = (beta - alpha)/beta and
+//     v = (x_j - beta e_j)/(alpha - beta), the reflector's action on column c
+//     follows from the reduced sums alone: v^T x_c = (g_c - beta x_c(j)) /
+//     (alpha - beta).  Degenerate columns follow the conventions of the
+//     oracle: tau = 0 for a zero column or a column of length one.
+//   * after a slab: the partial products V_s^T [V_0 .. V_s | A_rest] are
+//     reduce-scattered (two barriers); they give the Gram rows needed for T
+//     and W = V_s^T A_rest, which updates the rest of the panel as
+//     A_rest <- A_rest - V_s (T_s^T W).
+#include "common.h"
+
+namespace rq {
+
+namespace {
+
+constexpr int W = kPanelW;
+constexpr int kPThreads = 256;
+constexpr size_t kLdsDoubles = 20480 - 256;
+
+__device__ void flag_nonfinite(int32_t *info, int block_index) {
+  if (!info) return;
+  atomicExch(&info[0], 1);
+  atomicCAS(&info[1], 0, block_index + 1);
+}
+
+__global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw, GridBarrier gb) {
+  extern __shared__ double lds[];
+  const int nb = p.nb;
+  const int ldz = rpw + 1;
+  double *X = lds;                          // W x rpw   slab (own rows), column c at X + c*rpw
+  double *Zc = X + (size_t)W * rpw;         // W x ldz   staged columns
+  double *Wp = Zc + (size_t)W * ldz;        // W x nb    T_s^T V_s^T A_rest, row t at Wp + t*nb
+  double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
+  double *sc = Ts + W * W;                  // 320       reduction scratch
+  double *taus = sc + 320;                  // W
+  __shared__ double s_beta, s_tau, s_scale;
+
+  const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
+  const int64_t rbeg = (int64_t)wg * rpw;
+  const int nrow = (int)max((int64_t)0, min((int64_t)rpw, p.mi - rbeg));
+  const int nslab = (nb + W - 1) / W;
+  double *part_cs = p.part;                                   // [2][nwg][2W]
+  double *part_up = p.part + (size_t)2 * nwg * 2 * W;         // [nwg][W*nb]
+  unsigned gen = 0;
+  bool ok = true;
+  int step = 0;
+
+  for (int s = 0; s < nslab && ok; ++s) {
+    const int cs = s * W, ws = min(W, nb - cs);
+    for (int idx = t; idx < ws * nrow; idx += kPThreads) {
+      const int c = idx / nrow, r = idx % nrow;
+      X[c * rpw + r] = p.P[(rbeg + r) + (int64_t)(cs + c) * p.ldp];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < ws && ok; ++jj, ++step) {
+      const int64_t j = cs + jj;
+      const int E = ws - jj;
+      const int buf = step & 1;
+      // partial sums of x_j^T x_c (own rows >= j) and x_c(j)
+      {
+        const int c = jj + (t >> 3), sub = t & 7;
+        double g = 0.0;
+        if (c < ws) {
+          int r0 = (int)max((int64_t)0, j - rbeg);
+          for (int r = r0 + sub; r < nrow; r += 8) g += X[jj * rpw + r] * X[c * rpw + r];
+        }
+        g += __shfl_xor(g, 1, 64);
+        g += __shfl_xor(g, 2, 64);
+        g += __shfl_xor(g, 4, 64);
+        if (sub == 0 && c < ws) {
+          const double h = (j >= rbeg && j < rbeg + nrow) ? X[c * rpw + (int)(j - rbeg)] : 0.0;
+          double *mp = part_cs + ((size_t)buf * nwg + wg) * 2 * W;
+          mp[c - jj] = g;
+          mp[W + (c - jj)] = h;
+        }
+      }
+      ok = grid_sync(gb, gen);
+      if (!ok) break;
+      // fixed-order reduction: 4 groups of workgroups, then the groups in order
+      {
+        const int e = t & 63, grp = t >> 6;
+        const bool valid = (e < W) ? (e < E) : (e - W < E);
+        double acc = 0.0;
+        if (valid)
+          for (int w2 = grp; w2 < nwg; w2 += 4) acc += part_cs[((size_t)buf * nwg + w2) * 2 * W + e];
+        sc[grp * 64 + e] = acc;
+        __syncthreads();
+        if (t < 64) sc[t] = ((sc[t] + sc[64 + t]) + sc[128 + t]) + sc[192 + t];
+        __syncthreads();
+      }
+      if (t == 0) {
+        const double alpha = sc[W], nrm2 = sc[0];
+        double beta = alpha, tau = 0.0, scale = 1.0;
+        if (!(nrm2 == nrm2) || nrm2 > 1.79e308) flag_nonfinite(p.info, p.block_index);
+        if (j < p.mi - 1) {
+          if (nrm2 != 0.0) {
+            beta = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(nrm2);
+            tau = (beta - alpha) / beta;
+            scale = alpha - beta;
+          } else {
+            beta = 0.0;
+          }
+        }
+        s_beta = beta; s_tau = tau; s_scale = scale;
+        taus[jj] = tau;
+        if (wg == 0) p.tau[j] = tau;
+      }
+      __syncthreads();
+      const double beta = s_beta, tau = s_tau, scale = s_scale;
+      // f_c = tau v^T x_c for the columns right of jj (index c - jj in sc[256..])
+      if (t > 0 && t < E) sc[256 + t] = tau * ((sc[t] - beta * sc[W + t]) / scale);
+      __syncthreads();
+      for (int r = t; r < nrow; r += kPThreads) {
+        const int64_t rg = rbeg + r;
+        if (rg < j) continue;
+        if (rg == j) {
+          if (tau != 0.0)
+            for (int c = jj + 1; c < ws; ++c) X[c * rpw + r] -= sc[256 + c - jj];
+          X[jj * rpw + r] = beta;
+        } else if (tau != 0.0) {
+          const double vr = X[jj * rpw + r] / scale;
+          X[jj * rpw + r] = vr;
+          for (int c = jj + 1; c < ws; ++c) X[c * rpw + r] -= sc[256 + c - jj] * vr;
+        }
+      }
+      __syncthreads();
+    }
+    if (!ok) break;
+    // write the slab back (R and the stored vectors) and the explicit V;
+    // then turn X into the explicit unit-lower V_s
+    for (int idx = t; idx < ws * nrow; idx += kPThreads) {
+      const int c = idx / nrow, r = idx % nrow;
+      const int64_t rg = rbeg + r, jc = cs + c;
+      const double x = X[c * rpw + r];
+      p.P[rg + jc * p.ldp] = x;
+      const double ve = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
+      p.V[rg + jc * p.ldv] = ve;
+      X[c * rpw + r] = ve;
+    }
+    for (int idx = t; idx < (W - ws) * rpw; idx += kPThreads) X[ws * rpw + idx] = 0.0;
+    __syncthreads();
+    // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest]
+    double *mypart = part_up + (size_t)wg * W * nb;
+    for (int cc = 0; cc < nb; cc += 32) {
+      for (int idx = t; idx < 32 * nrow; idx += kPThreads) {
+        const int c = idx / nrow, r = idx % nrow, col = cc + c;
+        double z = 0.0;
+        if (col < nb) {
+          if (col >= cs + ws) z = p.P[(rbeg + r) + (int64_t)col * p.ldp];
+          else if (col >= cs) z = X[(col - cs) * rpw + r];
+          else z = p.V[(rbeg + r) + (int64_t)col * p.ldv];
+        }
+        Zc[c * ldz + r] = z;
+      }
+      __syncthreads();
+      {
+        const int c = t & 31, tg = t >> 5;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const double *x0 = X + (tg * 4 + 0) * rpw, *x1 = X + (tg * 4 + 1) * rpw;
+        const double *x2 = X + (tg * 4 + 2) * rpw, *x3 = X + (tg * 4 + 3) * rpw;
+        const double *zc = Zc + c * ldz;
+        for (int r = 0; r < nrow; ++r) {
+          const double z = zc[r];
+          a0 += x0[r] * z; a1 += x1[r] * z; a2 += x2[r] * z; a3 += x3[r] * z;
+        }
+        if (cc + c < nb) {
+          const double av[4] = {a0, a1, a2, a3};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (tg * 4 + q < ws) mypart[(tg * 4 + q) * nb + cc + c] = av[q];
+        }
+      }
+      __syncthreads();
+    }
+    ok = grid_sync(gb, gen);
+    if (!ok) break;
+    {
+      const int E = ws * nb;
+      const int per = (E + nwg - 1) / nwg;
+      const int beg = wg * per, end = min(E, beg + per);
+      for (int e = beg + t; e < end; e += kPThreads) {
+        double acc = 0.0;
+        for (int w2 = 0; w2 < nwg; ++w2) acc += part_up[(size_t)w2 * W * nb + e];
+        p.red[e] = acc;
+      }
+    }
+    ok = grid_sync(gb, gen);
+    if (!ok) break;
+    // Gram rows -> S (column j = cs + tt holds v_q^T v_j for q < cs + ws)
+    if (wg == 0)
+      for (int idx = t; idx < ws * (cs + ws); idx += kPThreads) {
+        const int tt = idx / (cs + ws), q = idx % (cs + ws);
+        p.S[q + (int64_t)(cs + tt) * nb] = p.red[tt * nb + q];
+      }
+    // T_s by the forward recurrence T(0:tt, tt) = -tau_tt T(0:tt, 0:tt) V^T v_tt
+    for (int tt = 0; tt < ws; ++tt) {
+      if (t < tt) {
+        double acc = 0.0;
+        for (int u = t; u < tt; ++u) acc += Ts[t + u * W] * p.red[u * nb + cs + tt];
+        Ts[t + tt * W] = -taus[tt] * acc;
+      } else if (t == tt) {
+        Ts[tt + tt * W] = taus[tt];
+      } else if (t < W) {
+        Ts[t + tt * W] = 0.0;
+      }
+      __syncthreads();
+    }
+    const int rest = nb - (cs + ws);
+    if (rest > 0) {
+      // Wp = T_s^T (V_s^T A_rest)
+      for (int idx = t; idx < ws * rest; idx += kPThreads) {
+        const int tt = idx / rest, c = idx % rest;
+        double acc = 0.0;
+        for (int u = 0; u <= tt; ++u) acc += Ts[u + tt * W] * p.red[u * nb + cs + ws + c];
+        Wp[tt * nb + c] = acc;
+      }
+      __syncthreads();
+      // A_rest(own rows) -= V_s Wp
+      for (int idx = t; idx < nrow * rest; idx += kPThreads) {
+        const int r = idx % nrow, c = idx / nrow;
+        double *ap = p.P + (rbeg + r) + (int64_t)(cs + ws + c) * p.ldp;
+        double acc = *ap;
+        for (int tt = 0; tt < ws; ++tt) acc -= X[tt * rpw + r] * Wp[tt * nb + c];
+        *ap = acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok && p.info && t == 0) atomicExch(&p.info[2], 1);
+}
+
+size_t panel_lds_doubles(int rpw, int nb) {
+  return (size_t)W * rpw + (size_t)W * (rpw + 1) + (size_t)W * nb + W * W + 320 + W;
+}
+
+// T (nb x nb, upper triangular) from tau and the Gram matrix S.  Row i of T
+// depends only on earlier entries of the same row: T(i, j) = -tau_j *
+// sum_{q=i}^{j-1} T(i, q) S(q, j), T(i, i) = tau_i.  One thread per row.
+__global__ __launch_bounds__(64) void wy_t_kernel(int nb, const double *__restrict__ tau,
+                                                  const double *__restrict__ S, double *__restrict__ T,
+                                                  int64_t ldt) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= nb) return;
+  for (int j = 0; j < i; ++j) T[i + (int64_t)j * ldt] = 0.0;
+  T[i + (int64_t)i * ldt] = tau[i];
+  for (int j = i + 1; j < nb; ++j) {
+    double acc = 0.0;
+    const double *sj = S + (int64_t)j * nb;
+    for (int q = i; q < j; ++q) acc += T[i + (int64_t)q * ldt] * sj[q];
+    T[i + (int64_t)j * ldt] = -tau[j] * acc;
+  }
+}
+
+}  // namespace
+
+int panel_config(int64_t mi, int nb, int *rpw) {
+  if (mi < 1 || nb < 1 || nb > 512) return 0;
+  int64_t nwg = (mi + 31) / 32;
+  if (nwg > 64) nwg = 64;
+  for (;; ++nwg) {
+    if (nwg > 256) return 0;
+    const int64_t r = (mi + nwg - 1) / nwg;
+    if (panel_lds_doubles((int)r, nb) <= kLdsDoubles) {
+      *rpw = (int)r;
+      return (int)((mi + r - 1) / r);
+    }
+  }
+}
+
+size_t panel_part_doubles(int nwg, int nb) { return (size_t)2 * nwg * 2 * W + (size_t)nwg * W * nb; }
+
+hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
+  int rpw = 0;
+  const int nwg = panel_config(p.mi, p.nb, &rpw);
+  if (nwg == 0) return hipErrorInvalidValue;
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void *)panel_qr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kLdsDoubles * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  const size_t lds = panel_lds_doubles(rpw, p.nb) * sizeof(double);
+  PanelQR pp = p;
+  GridBarrier gb{p.bar, p.abort_flag};
+  void *args[] = {&pp, &rpw, &gb};
+  return hipLaunchCooperativeKernel((const void *)panel_qr_kernel, dim3(nwg), dim3(kPThreads), args,
+                                    (unsigned)lds, s);
+}
+
+hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(wy_t_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, nb, tau, S, T, ldt);
+  return hipGetLastError();
+}
+
+}  // namespace rq

@@ -1,0 +1,284 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Every case draws a seeded synthetic input, runs the library on the GPU and
+the oracle on the CPU with the same sketches, and compares:
+  * pivots: bit-exact on every position fixed by a separated decision of the
+    oracle (tests/parity.py), for the permutation form;
+  * R(0:p, :) P^T on that prefix p: relative Frobenius difference <= 1e-10
+    (rows are not forward-stable beyond that, so the full R is compared
+    through invariants instead);
+  * invariants of any correct output: |A P - Q R|_F / |A|_F <= 1e-13 (1e-12
+    at n = 8192), |Q^T Q - I|_F <= 1e-12, with Q rebuilt from the stored
+    reflectors by LAPACK's orgqr in torch, independently of this library.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1505_08115_amd as R
+import workloads as W
+from oracle import philox
+from oracle import rqrcp as O
+from tests.parity import r_times_pt, separated_prefix, sign_rows
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _oracle_G(seed, m, n, b, p, k, tail_classical):
+    """Concatenated per-block sketches in the layout of rqrcp_opts_t.G."""
+    blocks = []
+    nb = -(-k // b)
+    for i in range(nb):
+        r0 = i * b
+        if tail_classical and k == n and r0 + b >= n:
+            break
+        blocks.append(philox.sketch_block(seed, i, b + p, r0, m - r0))
+    return blocks
+
+
+def _g_hook(blocks):
+    flat = np.concatenate([g.ravel(order="F") for g in blocks]) if blocks else np.zeros(1)
+    return torch.tensor(flat, dtype=torch.float64, device=DEV)
+
+
+def _invariants(A_np, Fz, tol_res=1e-13, tol_orth=1e-12):
+    m, n = A_np.shape
+    F = Fz.F
+    k = Fz.rank
+    Q = torch.linalg.householder_product(F[:, :k].contiguous(), Fz.tau[:k].contiguous())
+    Rk = torch.triu(F[:k, :])
+    A = torch.tensor(A_np, device=DEV)
+    if Fz.pivot == "perm":
+        AP = A[:, Fz.jpvt.long()]
+    else:
+        AP = R.apply_p(Fz, R.colmajor(A.clone()), trans=False)
+    nA = torch.linalg.norm(A)
+    if k == n:
+        res = torch.linalg.norm(AP - Q @ Rk) / nA
+    else:
+        # truncated: A P = Q_k R_k + [0, R_22 block]; check the leading rows
+        res = torch.linalg.norm(Q.T @ AP - Rk) / nA
+    orth = torch.linalg.norm(Q.T @ Q - torch.eye(k, device=DEV, dtype=torch.float64))
+    assert float(res) <= tol_res, f"residual {float(res):.3e}"
+    assert float(orth) <= tol_orth, f"orthogonality {float(orth):.3e}"
+    if Fz.pivot == "perm":
+        assert sorted(Fz.jpvt.cpu().tolist()) == list(range(n))
+    return float(res), float(orth)
+
+
+def _compare(A_np, Fz, ref, expect_prefix=None):
+    n = A_np.shape[1]
+    pre = separated_prefix(ref)
+    jg = Fz.jpvt.cpu().numpy()
+    if Fz.pivot == "perm":
+        assert list(jg[:pre]) == list(ref["jpvt"][:pre]), f"pivots differ before position {pre}"
+    else:
+        pre = ref["rank"]
+    if expect_prefix is not None:
+        assert pre >= expect_prefix, f"only {pre} separated decisions"
+    rows = min(pre, ref["rank"])
+    if rows > 0:
+        Fg = Fz.F.cpu().numpy()
+        if Fz.pivot == "perm":
+            Rg, Ro = r_times_pt(Fg, jg, rows), r_times_pt(ref["F"], ref["jpvt"], rows)
+        else:
+            Rg, Ro = sign_rows(np.triu(Fg[:rows])), sign_rows(np.triu(ref["F"][:rows]))
+        d = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+        assert d <= 1e-10, f"R differs by {d:.3e} on the separated prefix"
+    return pre
+
+
+def test_library_is_the_in_tree_native_build():
+    L = R.load_library()
+    assert L._name == R.LIB_PATH
+    for name in R.EXPORTS:
+        assert hasattr(L, name)
+
+
+@pytest.mark.parametrize("seed,block,nsample,row0,nrows", [(1, 0, 40, 0, 512), (6, 3, 266, 768, 7424), (2**63 + 5, 7, 3, 5, 9)])
+def test_sketch_matches_oracle_generator(seed, block, nsample, row0, nrows):
+    G = R.sketch(seed, block, nsample, row0, nrows).cpu().numpy()
+    Go = philox.sketch_block(seed, block, nsample, row0, nrows)
+    # same Philox words and uniforms; log/cos differ by a few ulp between libms
+    np.testing.assert_allclose(G, Go, rtol=1e-14, atol=1e-15)
+
+
+SMALL = [
+    # m, n, b, p, pivot, rank, tail
+    (64, 64, 8, 4, "perm", 0, "classical"),
+    (300, 250, 32, 5, "perm", 0, "classical"),     # ragged last block, m > n
+    (200, 200, 32, 0, "perm", 0, "classical"),     # no oversampling
+    (130, 100, 128, 3, "perm", 0, "classical"),    # b >= n: one block, the tail
+    (257, 257, 16, 8, "perm", 0, "sampled"),       # sampled tail
+    (400, 300, 64, 10, "perm", 100, "classical"),  # truncated rank, partial block
+    (96, 96, 16, 4, "ortho", 0, "classical"),
+    (300, 210, 32, 6, "ortho", 0, "classical"),
+    (256, 256, 64, 10, "ortho", 100, "classical"),
+]
+
+
+@pytest.mark.parametrize("m,n,b,p,pivot,rank,tail", SMALL)
+def test_factor_matches_oracle_with_shared_sketch(m, n, b, p, pivot, rank, tail):
+    s = W.sigma_geometric(n, 6.0)
+    A = W.make_matrix(m, n, s, seed=m + n + b).numpy()
+    k = n if rank == 0 else rank
+    blocks = _oracle_G(11, m, n, b, p, k, tail == "classical" and pivot == "perm")
+    ref = O.rqrcp(A, b, p, seed=11, pivot=pivot, rank=rank, tail=tail, G=blocks or None)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=p, seed=0, pivot=pivot, rank=rank, tail=tail,
+                  G=_g_hook(blocks))
+    torch.cuda.synchronize()
+    _compare(A, Fz, ref)
+    _invariants(A, Fz)
+    np.testing.assert_allclose(np.abs(Fz.tau.cpu().numpy()[:k]), np.abs(ref["tau"][:k]), atol=1e-8)
+
+
+@pytest.mark.parametrize("m,n,b,p", [(128, 128, 16, 4), (512, 384, 64, 8)])
+def test_factor_draws_the_same_sketch_as_the_oracle(m, n, b, p):
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 5.0), seed=3).numpy()
+    ref = O.rqrcp(A, b, p, seed=12345)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=p, seed=12345)
+    torch.cuda.synchronize()
+    assert _compare(A, Fz, ref) >= n // 2
+    _invariants(A, Fz)
+
+
+def test_C1_full_parity():
+    w = W.WORKLOADS["C1"]
+    A = W.workload_matrix(w).numpy()
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed)
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=w.b, oversample=w.p, seed=w.seed, info=info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 0, 0, 0]
+    pre = _compare(A, Fz, ref)
+    assert pre == w.n, f"C1 should be fully separated, prefix {pre}"
+    assert list(Fz.jpvt.cpu().numpy()) == list(ref["jpvt"])
+    _invariants(A, Fz)
+    # R and T blocks match the oracle everywhere (same pivots)
+    np.testing.assert_allclose(sign_rows(np.triu(Fz.F.cpu().numpy())), sign_rows(np.triu(ref["F"])), rtol=0,
+                               atol=1e-12)
+    # T blocks: block i is computed from a trailing matrix known to relative
+    # accuracy ~ u |A| / |X_i|, so the bound scales with that ratio
+    Tg = Fz.T.cpu().numpy().reshape(-1, w.b, w.b)
+    nA = ref["xnorm"][0]
+    for i, To in enumerate(ref["T"]):
+        bi = To.shape[0]
+        Tgi = Tg[i].T[:bi, :bi]     # column-major block
+        tol = max(1e-12, 1e4 * 2.0 ** -53 * nA / ref["xnorm"][i])
+        assert np.linalg.norm(Tgi - To) <= tol * np.linalg.norm(To), f"T block {i}"
+
+
+def test_zero_matrix_and_exact_rank():
+    # zero input: every norm ties at 0, pivots stay in place, R = 0
+    Z = np.zeros((70, 50))
+    Fz = R.factor(torch.tensor(Z, device=DEV), block=16, oversample=4, seed=1)
+    torch.cuda.synchronize()
+    assert Fz.jpvt.cpu().tolist() == list(range(50))
+    assert float(torch.abs(Fz.F).max()) == 0.0
+    assert float(torch.abs(Fz.tau).max()) == 0.0
+    # exactly representable rank-13 input: the trailing block is roundoff
+    A = W.integer_rank_k(90, 90, 13, seed=4)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=8, oversample=4, seed=2)
+    torch.cuda.synchronize()
+    Rg = np.triu(Fz.F.cpu().numpy())
+    assert np.linalg.norm(Rg[13:, 13:]) <= 100 * 2.0 ** -53 * np.sqrt(90) * np.linalg.norm(A)
+    _invariants(A, Fz)
+
+
+def test_nonfinite_input_raises_the_info_flag():
+    A = W.make_matrix(64, 64, W.sigma_geometric(64, 2.0), seed=1).numpy()
+    A[5, 7] = np.nan
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    R.factor(torch.tensor(A, device=DEV), block=16, oversample=4, seed=1, info=info)
+    torch.cuda.synchronize()
+    iv = info.cpu().tolist()
+    assert iv[0] == 1 and iv[1] >= 1 and iv[2] == 0
+
+
+@pytest.mark.parametrize("name", ["C2", "C2r"])
+def test_C2_parity_and_exact_rank(name):
+    w = W.WORKLOADS[name]
+    A_dev = W.workload_matrix(w, device=DEV)
+    A = A_dev.cpu().numpy()
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed)
+    torch.cuda.synchronize()
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed)
+    pre = _compare(A, Fz, ref)
+    assert pre >= 512, f"separated prefix only {pre}"
+    _invariants(A, Fz)
+    if name == "C2r":
+        Rg = np.triu(Fz.F.cpu().numpy())
+        tail = np.linalg.norm(Rg[1000:, 1000:])
+        assert tail <= 100 * 2.0 ** -53 * np.sqrt(w.n) * np.linalg.norm(A), f"trailing block {tail:.3e}"
+
+
+def test_C3_subcase_ortho_tracks_singular_values():
+    w = W.WORKLOADS["C3s"]
+    A = W.workload_matrix(w).numpy()
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed, pivot="ortho")
+    Fz = R.factor(torch.tensor(A, device=DEV), block=w.b, oversample=w.p, seed=w.seed, pivot="ortho")
+    torch.cuda.synchronize()
+    _compare(A, Fz, ref)
+    _invariants(A, Fz)
+    sv = O.jacobi_singular_values(A)
+    dg = np.abs(np.diag(Fz.F.cpu().numpy()))
+    do = np.abs(np.diag(ref["F"]))
+    # |R_ii| of the GPU factorization tracks the oracle's relative to sigma_i
+    rank = int(np.sum(sv > sv[0] * 1e-13))
+    assert np.max(np.abs(dg[:rank] / sv[:rank] - do[:rank] / sv[:rank])) <= 1e-6
+    gamma = np.max(np.maximum(dg[:rank] / sv[:rank], sv[:rank] / dg[:rank]))
+    assert gamma <= 10 * np.sqrt(w.n), f"gamma {gamma:.3e}"
+
+
+def test_H1_full_size_properties_and_first_block_pivots():
+    """n = 8192 in the benchmark's configuration: invariants at full size,
+    and the first block's pivots against the oracle's sketch and QRCP."""
+    w = W.WORKLOADS["H1"]
+    A_dev = W.workload_matrix(w, device=DEV)
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed)
+    torch.cuda.synchronize()
+    m, n = A_dev.shape
+    _invariants(A_dev.cpu().numpy(), Fz, tol_res=1e-12, tol_orth=1e-11)
+    A = A_dev.cpu().numpy()
+    G0 = philox.sketch_block(w.seed, 0, w.b + w.p, 0, m)
+    Y = G0 @ A
+    piv, jp, _, mg = O.qrcp(Y, steps=w.b, record_margins=True)
+    sep = int(np.argmax(~(mg > 1e-10))) if np.any(~(mg > 1e-10)) else w.b
+    assert sep >= 200
+    assert list(Fz.jpvt.cpu().numpy()[:sep]) == list(jp[:sep])
+
+
+def test_apply_q_apply_p_lowrank_match_oracle():
+    m, n, b, k = 300, 240, 32, 100
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 6.0), seed=9).numpy()
+    for pivot in ("perm", "ortho"):
+        blocks = _oracle_G(5, m, n, b, 6, k, False)
+        ref = O.rqrcp(A, b, 6, seed=5, pivot=pivot, rank=k, G=blocks)
+        Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=6, pivot=pivot, rank=k, G=_g_hook(blocks))
+        C = W.gaussian_matrix(m, 17, seed=3).numpy()
+        for trans in (False, True):
+            got = R.apply_q(Fz, R.colmajor(torch.tensor(C, device=DEV)), trans=trans).cpu().numpy()
+            np.testing.assert_allclose(got, O.apply_q(ref, C, trans), atol=1e-12)
+        D = W.gaussian_matrix(9, n, seed=4).numpy()
+        P = O.form_p(ref)
+        got = R.apply_p(Fz, R.colmajor(torch.tensor(D, device=DEV)), trans=False).cpu().numpy()
+        np.testing.assert_allclose(got, D @ P, atol=1e-12)
+        got = R.apply_p(Fz, R.colmajor(torch.tensor(D, device=DEV)), trans=True).cpu().numpy()
+        np.testing.assert_allclose(got, D @ P.T, atol=1e-12)
+        for kk in (k, 37):
+            Ak = R.lowrank(Fz, kk).cpu().numpy()
+            np.testing.assert_allclose(Ak, O.lowrank(ref, kk), atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n,k,b", [(120, 90, 20, 8), (300, 300, 64, 32)])
+def test_lowrank_backward_matches_oracle_gradient(m, n, k, b):
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 3.0), seed=m).numpy()
+    B = W.gaussian_matrix(m, n, seed=n).numpy()
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=5, seed=7, rank=k)
+    jp = Fz.jpvt.cpu().numpy()
+    Ak = R.lowrank(Fz, k)
+    Gbar = 2 * (Ak - torch.tensor(B, device=DEV))
+    dA = R.lowrank_backward(R.colmajor(torch.tensor(A, device=DEV)), Fz, R.colmajor(Gbar), k).cpu().numpy()
+    ref = O.lowrank_grad(A, jp, k, Gbar.cpu().numpy())
+    np.testing.assert_allclose(dA, ref, atol=1e-10 * np.abs(ref).max())
