@@ -107,7 +107,7 @@ def _column_norms(A, j):
     return np.sqrt(np.einsum("ij,ij->j", A[j:, j:], A[j:, j:]))
 
 
-def qrcp(A, steps=None, record_margins=False):
+def qrcp(A, steps=None, record_margins=False, tops=None):
     """Classical QRCP (Fig. 2) of A in place, running `steps` pivot steps.
 
     Returns (piv, jpvt, tau, margins):
@@ -116,6 +116,8 @@ def qrcp(A, steps=None, record_margins=False):
       tau     : reflector scalars,
       margins : per step, (nu_1^2 - nu_2^2) / nu_1^2 for the top two
                 remaining norms (inf when one candidate, 0 when nu_1 = 0).
+    If `tops` is a list, the largest remaining norm nu_1 of every step is
+    appended to it.
     """
     m, n = A.shape
     if steps is None:
@@ -127,6 +129,8 @@ def qrcp(A, steps=None, record_margins=False):
     for j in range(steps):
         nu = _column_norms(A, j)
         jj = int(np.argmax(nu))          # first maximum = lowest position
+        if tops is not None:
+            tops.append(float(nu[jj]))
         if record_margins:
             top = nu[jj]
             rest = np.delete(nu, jj)
@@ -199,8 +203,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
     Output keys: F (R on and above the diagonal, Householder vectors below),
     tau, T (list of per-block T), jpvt, S (list of (V_S, tau_S, T_S) per block
     for ortho), piv (list of per-block swap lists), margins (list), xnorm
-    (Frobenius norm of each block's trailing matrix X_i), and, with
-    trace=True, Y (list of per-block samples before factoring).
+    (Frobenius norm of each block's trailing matrix X_i), ynorm (Frobenius
+    norm of the matrix each pivoted QR ran on), tops (per block, the largest
+    remaining norm at every pivot step), and, with trace=True, Y (list of
+    per-block samples before factoring).
     """
     A = np.array(A, dtype=np.float64, copy=True)
     m, n = A.shape
@@ -211,7 +217,8 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         raise ValueError("rank out of range")
     jpvt = np.arange(n)
     tau = np.zeros(k)
-    out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": [], "xnorm": []}
+    out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": [], "xnorm": [], "ynorm": [],
+           "tops": []}
     nblocks = -(-k // b)
     for i in range(nblocks):
         r0 = i * b
@@ -224,7 +231,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         if is_tail and tail == "classical" and pivot == "perm":
             # last block of Fig. 3: classical QRCP of the remaining block
             Xc = X.copy()
-            piv, jp, t, mg = qrcp(Xc, steps=bi, record_margins=True)
+            out["ynorm"].append(float(np.linalg.norm(Xc)))
+            tp = []
+            piv, jp, t, mg = qrcp(Xc, steps=bi, record_margins=True, tops=tp)
+            out["tops"].append(np.array(tp))
             A[:r0, r0:] = A[:r0, r0:][:, jp]
             A[r0:, r0:] = Xc
             jpvt[r0:] = jpvt[r0:][jp]
@@ -243,7 +253,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
             out["Y"].append(Y.copy())
         if pivot == "perm":
             # eq. Yrows: classical QRCP of Y, first b_i steps only
-            piv, jp, _, mg = qrcp(Y, steps=bi, record_margins=True)
+            out["ynorm"].append(float(np.linalg.norm(Y)))
+            tp = []
+            piv, jp, _, mg = qrcp(Y, steps=bi, record_margins=True, tops=tp)
+            out["tops"].append(np.array(tp))
             for j in range(bi):                    # P-tilde on all m rows
                 jj = int(piv[j])
                 if jj != j:

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -20,6 +21,7 @@ struct rqrcp_timing_rec {
 struct rqrcp_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
+  uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
   bool timing = false;
   std::vector<hipEvent_t> free_events;
@@ -72,7 +74,9 @@ size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
 
 struct FactorPlan {
   int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
-  bool ortho = false, fixed = false, classical_tail = false;
+  bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
+  // FP32-storage buffers
+  size_t Pw = 0, V32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
   int nslots = 0;
   // byte offsets into the workspace
   size_t G = 0, Y = 0, YT = 0, Vb = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
@@ -104,8 +108,9 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->fixed_pivots != 0 && o->fixed_pivots != 1) return fail(h, RQRCP_ERR_ARG, "opts.fixed_pivots must be 0 or 1");
   if (o->fixed_pivots && o->pivot == RQRCP_PIVOT_ORTHO)
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.fixed_pivots applies to the permutation form only");
-  if (dt == RQRCP_F32) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: F32 storage is not available in this build");
   FactorPlan P;
+  P.f32 = dt == RQRCP_F32;
+  P.mixed = o->precision == RQRCP_PREC_MIXED;
   P.m = m; P.n = n; P.b = o->block; P.p = o->oversample;
   P.k = o->rank == 0 ? n : o->rank;
   P.ks = P.b + P.p;
@@ -116,7 +121,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
   if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
 
-  size_t Yd = 0, gpart = 0, ppart = 0;
+  size_t Yd = 0, gpart = 0, ppart = 0, gpart32 = 0, spart = 0;
   int qnwg = 0;
   int64_t qk = 1;
   for (int64_t i = 0; i < P.nblocks; ++i) {
@@ -135,9 +140,15 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
         Yd = std::max(Yd, (size_t)(mi * ni));
       } else {
         Yd = std::max(Yd, (size_t)(P.ks * ni));
-        gpart = std::max(gpart, gemm_part_doubles(P.ortho ? bi : P.ks, ni, mi));
+        const int64_t yrows = P.ortho ? bi : P.ks;
+        gpart = std::max(gpart, gemm_part_doubles(yrows, ni, mi));
+        if (P.f32 && P.mixed) spart = std::max(spart, sample_bf16_part_floats(yrows, ni, mi));
+        if (P.f32 && !P.mixed) gpart32 = std::max(gpart32, gemm_part_doubles(yrows, ni, mi));
         if (P.ortho) {
           gpart = std::max(gpart, gemm_part_doubles(m, bi, bi));
+          gpart32 = std::max(gpart32, gemm_part_doubles(m, bi, bi));
+          gpart32 = std::max(gpart32, gemm_part_doubles(m, bi, ni));
+          gpart32 = std::max(gpart32, gemm_part_doubles(m, ni, bi));
           const int pn2 = panel_config(ni, (int)bi, &rpw);
           if (pn2 == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "sketch too large for the panel kernel");
           ppart = std::max(ppart, panel_part_doubles(pn2, (int)bi));
@@ -156,8 +167,11 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     if (ni > bi) {
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, mi));
       gpart = std::max(gpart, gemm_part_doubles(mi, ni - bi, bi));
+      gpart32 = std::max(gpart32, gemm_part_doubles(bi, ni - bi, mi));
+      gpart32 = std::max(gpart32, gemm_part_doubles(mi, ni - bi, bi));
     }
   }
+  if (!P.f32) gpart32 = 0;
   P.Y_doubles = Yd;
   P.nslots = (int)(3 * P.nblocks + 4);
   Bump w;
@@ -178,10 +192,25 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.dest = w.take((size_t)n * 4);
   P.moved = w.take((size_t)2 * P.b * 4);
   P.mcnt = w.take(4 * 64);
-  P.tmp = w.take(P.ortho || P.fixed ? 0 : (size_t)m * 2 * P.b * d);
+  const size_t es = P.f32 ? 4 : 8;   // storage element size
+  P.tmp = w.take(P.ortho || P.fixed ? 0 : (size_t)m * 2 * P.b * es);
   P.jtmp = w.take((size_t)2 * P.b * 4);
   P.bars = w.take((size_t)P.nslots * kSlotWords * 4);
-  P.Acopy = w.take(P.fixed ? (size_t)m * n * d : 0);
+  P.Acopy = w.take(P.fixed ? (size_t)m * n * es : 0);
+  if (P.f32) {
+    P.Pw = w.take((size_t)m * P.b * d);
+    P.V32 = w.take((size_t)m * P.b * 4);
+    P.Vt32 = w.take((size_t)m * P.b * 4);
+    P.W32 = w.take((size_t)P.b * n * 4);
+    P.gpart32 = w.take(gpart32 * 4);
+    const bool sampled = !P.fixed;
+    P.Gb = w.take(sampled && P.mixed ? (size_t)P.ks * m * 2 : 0);
+    P.spart = w.take(spart * 4);
+    P.G32 = w.take(sampled && !P.mixed ? (size_t)P.ks * m * 4 : 0);
+    P.Y32 = w.take(sampled && !P.mixed ? (size_t)P.ks * n * 4 : 0);
+    P.VS32 = w.take(P.ortho ? (size_t)n * P.b * 4 : 0);
+    P.TS32 = w.take(P.ortho ? (size_t)P.b * P.b * 4 : 0);
+  }
   P.total = w.off + 256;
   *out = P;
   return RQRCP_OK;
@@ -275,9 +304,13 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, RQRCP_ERR_UNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", need gfx950");
   if (!prop.cooperativeLaunch) return fail(nullptr, RQRCP_ERR_UNSUPPORTED, "device lacks cooperative launch");
+  int khz = 0;
+  e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "hipDeviceGetAttribute(WallClockRate)");
   rqrcp_ctx *c = new rqrcp_ctx();
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->device = dev;
+  c->limit_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 2000ull;
   *h = c;
   return RQRCP_OK;
 }
@@ -358,6 +391,234 @@ rqrcp_status_t rqrcp_sketch(rqrcp_handle_t h, uint64_t seed, int64_t block, int6
     if (e_ != hipSuccess) return fail_hip(h, e_, where);  \
   } while (0)
 
+}  // extern "C"
+
+namespace rq {
+namespace {
+
+// The per-block loop of Fig. 3 for storage type T (double: FP64 throughout;
+// float: FP64 panel, T and pivoted QR of the sketch, FP32 matrix-core GEMMs,
+// BF16 sketch product in the mixed mode).
+template <typename T>
+rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_opts_t *o, T *A, int64_t lda,
+                           int32_t *jpvt, double *tau, double *Tout, double *S, void *work) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  hipStream_t s = h->stream;
+  const int64_t m = P.m, n = P.n, b = P.b, ks = P.ks;
+  double *G = at<double>(work, P.G), *Y = at<double>(work, P.Y), *YT = at<double>(work, P.YT);
+  double *Vb = at<double>(work, P.Vb), *Vt = at<double>(work, P.Vt), *Wb = at<double>(work, P.Wb);
+  double *gpart = at<double>(work, P.gpart), *Sg = at<double>(work, P.Sg);
+  double *ppart = at<double>(work, P.ppart), *pred = at<double>(work, P.pred);
+  double *qrec = at<double>(work, P.qrec), *qcand = at<double>(work, P.qcand);
+  int32_t *piv = at<int32_t>(work, P.piv), *dest = at<int32_t>(work, P.dest);
+  int32_t *moved = at<int32_t>(work, P.moved), *mcnt = at<int32_t>(work, P.mcnt);
+  T *tmp = at<T>(work, P.tmp);
+  int32_t *jtmp = at<int32_t>(work, P.jtmp);
+  unsigned *bars = at<unsigned>(work, P.bars);
+  // FP32-storage buffers
+  double *Pw = at<double>(work, P.Pw);
+  float *V32 = at<float>(work, P.V32), *Vt32 = at<float>(work, P.Vt32), *W32 = at<float>(work, P.W32);
+  float *gpart32 = at<float>(work, P.gpart32), *spart = at<float>(work, P.spart);
+  float *G32 = at<float>(work, P.G32), *Y32 = at<float>(work, P.Y32);
+  float *VS32 = at<float>(work, P.VS32), *TS32 = at<float>(work, P.TS32);
+  void *Gb = at<void>(work, P.Gb);
+  int32_t *info = o->info;
+
+  std::vector<size_t> vs_off(P.nblocks, 0);
+  size_t vs_total = 0;
+  for (int64_t i = 0; i < P.nblocks; ++i) {
+    vs_off[i] = vs_total;
+    vs_total += (size_t)(n - i * b) * b;
+  }
+  double *tauS = P.ortho ? S + vs_total : nullptr;
+  double *TS = P.ortho ? tauS + P.nblocks * b : nullptr;
+
+  CHK(launch_zero_u32(s, bars, (size_t)P.nslots * kSlotWords), "zero barrier state");
+  CHK(launch_zero_u32(s, Tout, (size_t)P.nblocks * b * b * 2), "zero T");
+  if (info) CHK(launch_zero_u32(s, info, 4), "zero info");
+  if (P.ortho) CHK(launch_zero_u32(s, S, (vs_total + P.nblocks * b + (size_t)P.nblocks * b * b) * 2), "zero S");
+  if (P.fixed) {
+    T *Ac = at<T>(work, P.Acopy);
+    CHK(launch_copy2d_t(s, A, lda, Ac, m, m, n), "copy A");
+    CHK(launch_gather_cols_t(s, Ac, m, m, n, jpvt, n, A, lda), "permute A by jpvt");
+  } else {
+    CHK(launch_iota(s, jpvt, n), "jpvt identity");
+  }
+  int slot = 0;
+  auto next_slot = [&](unsigned **bar, int **ab) {
+    unsigned *base = bars + (size_t)slot * kSlotWords;
+    ++slot;
+    *bar = base;
+    *ab = reinterpret_cast<int *>(base + kAbortWord);
+  };
+  auto run_qrcp = [&](double *Yp, int64_t ldy, int64_t k, int64_t ncols, int64_t steps, int64_t i) -> hipError_t {
+    hipError_t e = launch_zero_u32(s, mcnt, 1);
+    if (e != hipSuccess) return e;
+    QrcpSmall q{};
+    q.Y = Yp; q.ldy = ldy; q.k = (int)k; q.ncols = (int)ncols; q.nsteps = (int)steps;
+    q.piv = piv; q.dest = dest; q.moved = moved; q.moved_cnt = mcnt;
+    q.rec = qrec; q.cand = qcand; q.info = info; q.block_index = (int)i; q.limit_ticks = h->limit_ticks;
+    next_slot(&q.bar, &q.abort_flag);
+    return launch_qrcp_small(s, q);
+  };
+  size_t goff = 0;   // offset of the current block's sketch in opts.G
+
+  for (int64_t i = 0; i < P.nblocks; ++i) {
+    const int64_t r0 = i * b, bi = std::min(b, P.k - r0), mi = m - r0, ni = n - r0;
+    T *X = A + r0 + r0 * lda;
+    if (!P.fixed) {
+      if (block_is_classical_tail(P, i)) {
+        // last block of Fig. 3: classical QRCP of the remaining block
+        {
+          ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)mi, (double)ni, (double)bi), 16.0 * mi * ni);
+          CHK(launch_to_f64(s, X, lda, Y, mi, mi, ni), "copy last block");
+          CHK(run_qrcp(Y, mi, mi, ni, bi, i), "pivoted QR of the last block");
+        }
+        ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
+        CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
+            "move columns");
+      } else {
+        const double *Gi;
+        if (o->G) {
+          Gi = o->G + goff;
+        } else {
+          ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mi);
+          CHK(launch_sketch(s, o->seed, i, ks, r0, mi, G, ks), "sketch");
+          Gi = G;
+        }
+        goff += (size_t)ks * mi;
+        // Y_i = G_i X_i (Section 4.1, eq. defY).  The orthonormal variant runs
+        // the QR of Y_i^T without pivoting, whose first b_i reflectors depend
+        // only on the first b_i rows of Y_i: only those are formed.
+        const int64_t yrows = P.ortho ? bi : ks;
+        {
+          ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * yrows * ni * mi,
+                         (double)sizeof(T) * mi * ni + 8.0 * (yrows * mi + yrows * ni));
+          if constexpr (!F32) {
+            GemmF64 gy{false, false, yrows, ni, mi, Gi, ks, X, lda, Y, ks, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, gy, gpart), "sketch product");
+          } else if (P.mixed) {
+            CHK(launch_g_to_bf16(s, Gi, ks, yrows, mi, Gb, mi), "sketch to BF16");
+            CHK(launch_sample_bf16(s, yrows, ni, mi, Gb, mi, X, lda, spart, Y, ks), "BF16 sketch product");
+          } else {
+            CHK(launch_copy_f64_f32(s, Gi, ks, G32, ks, yrows, mi), "sketch to FP32");
+            GemmF32 gy{false, false, yrows, ni, mi, G32, ks, X, lda, Y32, ks, 1.f, 0.f};
+            CHK(launch_gemm<float>(s, gy, gpart32), "FP32 sketch product");
+            CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
+          }
+        }
+        if (!P.ortho) {
+          {
+            ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)ks, (double)ni, (double)bi), 8.0 * ks * ni);
+            CHK(run_qrcp(Y, ks, ks, ni, bi, i), "pivoted QR of the sketch");
+          }
+          ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
+          CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
+              "move columns");
+        } else {
+          // Section 4.2: unpivoted QR of Y_i^T, first b_i steps -> S_i = I - VS TS VS^T
+          double *VS = S + vs_off[i];
+          double *TSi = TS + (size_t)i * b * b;
+          ScopedTimer to(h, RQRCP_K_ORTHO, 2.0 * ni * bi * bi + 4.0 * m * ni * bi + 2.0 * m * bi * bi,
+                         (double)sizeof(T) * 3.0 * m * ni + 24.0 * ni * bi);
+          CHK(launch_transpose(s, Y, ks, YT, ni, bi, ni), "transpose sketch");
+          PanelQR pq{};
+          pq.P = YT; pq.ldp = ni; pq.mi = ni; pq.nb = (int)bi;
+          pq.tau = tauS + i * b; pq.V = VS; pq.ldv = ni; pq.S = Sg;
+          pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
+          next_slot(&pq.bar, &pq.abort_flag);
+          CHK(launch_panel_qr(s, pq), "QR of the sketch");
+          CHK(launch_wy_t(s, (int)bi, tauS + i * b, Sg, TSi, b), "T of the sketch reflectors");
+          // A(0:m, r0:n) <- A(0:m, r0:n) (I - VS TS VS^T), all m rows
+          T *Ac = A + r0 * lda;
+          if constexpr (!F32) {
+            GemmF64 g1{false, false, m, bi, ni, Ac, lda, VS, ni, Vb, m, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, g1, gpart), "A VS");
+            GemmF64 g2{false, false, m, bi, bi, Vb, m, TSi, b, Vt, m, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, g2, gpart), "(A VS) TS");
+            GemmF64 g3{false, true, m, ni, bi, Vt, m, VS, ni, Ac, lda, -1.0, 1.0};
+            CHK(launch_gemm_f64(s, g3, gpart), "A -= (A VS TS) VS^T");
+          } else {
+            CHK(launch_copy_f64_f32(s, VS, ni, VS32, ni, ni, bi), "VS to FP32");
+            CHK(launch_copy_f64_f32(s, TSi, b, TS32, b, bi, bi), "TS to FP32");
+            GemmF32 g1{false, false, m, bi, ni, Ac, lda, VS32, ni, V32, m, 1.f, 0.f};
+            CHK(launch_gemm<float>(s, g1, gpart32), "A VS");
+            GemmF32 g2{false, false, m, bi, bi, V32, m, TS32, b, Vt32, m, 1.f, 0.f};
+            CHK(launch_gemm<float>(s, g2, gpart32), "(A VS) TS");
+            GemmF32 g3{false, true, m, ni, bi, Vt32, m, VS32, ni, Ac, lda, -1.f, 1.f};
+            CHK(launch_gemm<float>(s, g3, gpart32), "A -= (A VS TS) VS^T");
+          }
+        }
+      }
+    }
+    // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi) in FP64
+    {
+      ScopedTimer tp(h, RQRCP_K_PANEL, 2.0 * mi * bi * bi - 2.0 * bi * bi * bi / 3.0, 24.0 * mi * bi);
+      PanelQR pq{};
+      if constexpr (F32) {
+        CHK(launch_copy_f32_f64(s, X, lda, Pw, mi, mi, bi), "panel to FP64");
+        pq.P = Pw; pq.ldp = mi;
+      } else {
+        pq.P = X; pq.ldp = lda;
+      }
+      pq.mi = mi; pq.nb = (int)bi;
+      pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+      pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
+      next_slot(&pq.bar, &pq.abort_flag);
+      CHK(launch_panel_qr(s, pq), "panel QR");
+      if constexpr (F32) CHK(launch_copy_f64_f32(s, Pw, mi, X, lda, mi, bi), "panel to FP32");
+    }
+    double *Ti = Tout + (size_t)i * b * b;
+    {
+      ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
+      CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
+    }
+    if (ni > bi) {
+      // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1)
+      T *C = X + bi * lda;
+      const double nc = (double)(ni - bi);
+      {
+        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
+        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
+        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
+        if constexpr (F32) {
+          CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
+          CHK(launch_copy_f64_f32(s, Vb, mi, V32, mi, mi, bi), "V to FP32");
+        }
+      }
+      {
+        ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
+                       (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
+        if constexpr (!F32) {
+          GemmF64 gw{true, false, bi, ni - bi, mi, Vb, mi, C, lda, Wb, bi, 1.0, 0.0};
+          CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
+        } else {
+          GemmF32 gw{true, false, bi, ni - bi, mi, V32, mi, C, lda, W32, bi, 1.f, 0.f};
+          CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
+        }
+      }
+      {
+        ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
+                       (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
+        if constexpr (!F32) {
+          GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0};
+          CHK(launch_gemm_f64(s, gu, gpart), "C -= (V T^T) W");
+        } else {
+          GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f};
+          CHK(launch_gemm<float>(s, gu, gpart32), "C -= (V T^T) W");
+        }
+      }
+    }
+  }
+  (void)piv;
+  return RQRCP_OK;
+}
+
+}  // namespace
+}  // namespace rq
+
+extern "C" {
+
 rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av, int64_t lda,
                             int32_t *jpvt, double *tau, double *T, double *S, const rqrcp_opts_t *o, void *work,
                             size_t work_bytes) {
@@ -375,166 +636,8 @@ rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64
   if (!work) return fail(h, RQRCP_ERR_WORKSPACE, "work is NULL");
   if (work_bytes < P.total) return fail(h, RQRCP_ERR_WORKSPACE, "work_bytes smaller than rqrcp_factor_sizes");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(h, RQRCP_ERR_WORKSPACE, "work must be 256-byte aligned");
-
-  hipStream_t s = h->stream;
-  double *A = static_cast<double *>(Av);
-  const int64_t b = P.b, ks = P.ks;
-  double *G = at<double>(work, P.G), *Y = at<double>(work, P.Y), *YT = at<double>(work, P.YT);
-  double *Vb = at<double>(work, P.Vb), *Vt = at<double>(work, P.Vt), *Wb = at<double>(work, P.Wb);
-  double *gpart = at<double>(work, P.gpart), *Sg = at<double>(work, P.Sg);
-  double *ppart = at<double>(work, P.ppart), *pred = at<double>(work, P.pred);
-  double *qrec = at<double>(work, P.qrec), *qcand = at<double>(work, P.qcand);
-  int32_t *piv = at<int32_t>(work, P.piv), *dest = at<int32_t>(work, P.dest);
-  int32_t *moved = at<int32_t>(work, P.moved), *mcnt = at<int32_t>(work, P.mcnt);
-  double *tmp = at<double>(work, P.tmp);
-  int32_t *jtmp = at<int32_t>(work, P.jtmp);
-  unsigned *bars = at<unsigned>(work, P.bars);
-  int32_t *info = o->info;
-
-  // VS blocks, tauS and TS inside S (ortho)
-  std::vector<size_t> vs_off(P.nblocks, 0);
-  size_t vs_total = 0;
-  for (int64_t i = 0; i < P.nblocks; ++i) {
-    vs_off[i] = vs_total;
-    vs_total += (size_t)(n - i * b) * b;
-  }
-  double *tauS = P.ortho ? S + vs_total : nullptr;
-  double *TS = P.ortho ? tauS + P.nblocks * b : nullptr;
-
-  CHK(launch_zero_u32(s, bars, (size_t)P.nslots * kSlotWords), "zero barrier state");
-  CHK(launch_zero_u32(s, T, (size_t)P.nblocks * b * b * 2), "zero T");
-  if (info) CHK(launch_zero_u32(s, info, 4), "zero info");
-  if (P.ortho) CHK(launch_zero_u32(s, S, (vs_total + P.nblocks * b + (size_t)P.nblocks * b * b) * 2), "zero S");
-  if (P.fixed) {
-    double *Ac = at<double>(work, P.Acopy);
-    CHK(launch_copy2d(s, A, lda, Ac, m, m, n), "copy A");
-    CHK(launch_gather_cols(s, Ac, m, m, n, jpvt, n, A, lda), "permute A by jpvt");
-  } else {
-    CHK(launch_iota(s, jpvt, n), "jpvt identity");
-  }
-  int slot = 0;
-  auto next_slot = [&](unsigned **bar, int **ab) {
-    unsigned *base = bars + (size_t)slot * kSlotWords;
-    ++slot;
-    *bar = base;
-    *ab = reinterpret_cast<int *>(base + kAbortWord);
-  };
-  size_t goff = 0;   // offset of the current block's sketch in opts.G
-
-  for (int64_t i = 0; i < P.nblocks; ++i) {
-    const int64_t r0 = i * b, bi = std::min(b, P.k - r0), mi = m - r0, ni = n - r0;
-    double *X = A + r0 + r0 * lda;
-    if (!P.fixed) {
-      if (block_is_classical_tail(P, i)) {
-        // last block of Fig. 3: classical QRCP of the remaining block
-        ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)mi, (double)ni, (double)bi), 16.0 * mi * ni);
-        CHK(launch_copy2d(s, X, lda, Y, mi, mi, ni), "copy last block");
-        CHK(launch_zero_u32(s, mcnt, 1), "zero move count");
-        QrcpSmall q{};
-        q.Y = Y; q.ldy = mi; q.k = (int)mi; q.ncols = (int)ni; q.nsteps = (int)bi;
-        q.piv = piv; q.dest = dest; q.moved = moved; q.moved_cnt = mcnt;
-        q.rec = qrec; q.cand = qcand; q.info = info; q.block_index = (int)i;
-        next_slot(&q.bar, &q.abort_flag);
-        CHK(launch_qrcp_small(s, q), "pivoted QR of the last block");
-        ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
-        CHK(launch_apply_moves(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp), "move columns");
-      } else {
-        const double *Gi;
-        int64_t ldg = ks;
-        if (o->G) {
-          Gi = o->G + goff;
-        } else {
-          ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mi);
-          CHK(launch_sketch(s, o->seed, i, ks, r0, mi, G, ks), "sketch");
-          Gi = G;
-        }
-        goff += (size_t)ks * mi;
-        // Y_i = G_i X_i (Section 4.1, eq. defY).  The orthonormal variant
-        // runs the QR of Y_i^T without pivoting, whose first b_i reflectors
-        // depend only on the first b_i rows of Y_i: only those are formed.
-        const int64_t yrows = P.ortho ? bi : ks;
-        GemmF64 gy{false, false, yrows, ni, mi, Gi, ldg, X, lda, Y, ks, 1.0, 0.0};
-        {
-          ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * yrows * ni * mi, 8.0 * (mi * ni + yrows * mi + yrows * ni));
-          CHK(launch_gemm_f64(s, gy, gpart), "sketch product");
-        }
-        if (!P.ortho) {
-          CHK(launch_zero_u32(s, mcnt, 1), "zero move count");
-          QrcpSmall q{};
-          q.Y = Y; q.ldy = ks; q.k = (int)ks; q.ncols = (int)ni; q.nsteps = (int)bi;
-          q.piv = piv; q.dest = dest; q.moved = moved; q.moved_cnt = mcnt;
-          q.rec = qrec; q.cand = qcand; q.info = info; q.block_index = (int)i;
-          next_slot(&q.bar, &q.abort_flag);
-          {
-            ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)ks, (double)ni, (double)bi), 8.0 * ks * ni);
-            CHK(launch_qrcp_small(s, q), "pivoted QR of the sketch");
-          }
-          ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
-          CHK(launch_apply_moves(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
-              "move columns");
-        } else {
-          // Section 4.2: unpivoted QR of Y_i^T, first b_i steps -> S_i = I - VS TS VS^T
-          double *VS = S + vs_off[i];
-          double *TSi = TS + (size_t)i * b * b;
-          ScopedTimer to(h, RQRCP_K_ORTHO, 2.0 * ni * bi * bi + 4.0 * m * ni * bi + 2.0 * m * bi * bi,
-                         8.0 * (3.0 * m * ni + 3.0 * ni * bi));
-          CHK(launch_transpose(s, Y, ks, YT, ni, bi, ni), "transpose sketch");
-          PanelQR pq{};
-          pq.P = YT; pq.ldp = ni; pq.mi = ni; pq.nb = (int)bi;
-          pq.tau = tauS + i * b; pq.V = VS; pq.ldv = ni; pq.S = Sg;
-          pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i;
-          next_slot(&pq.bar, &pq.abort_flag);
-          CHK(launch_panel_qr(s, pq), "QR of the sketch");
-          CHK(launch_wy_t(s, (int)bi, tauS + i * b, Sg, TSi, b), "T of the sketch reflectors");
-          // A(0:m, r0:n) <- A(0:m, r0:n) (I - VS TS VS^T), all m rows
-          double *Ac = A + r0 * lda;
-          GemmF64 g1{false, false, m, bi, ni, Ac, lda, VS, ni, Vb, m, 1.0, 0.0};
-          CHK(launch_gemm_f64(s, g1, gpart), "A VS");
-          GemmF64 g2{false, false, m, bi, bi, Vb, m, TSi, b, Vt, m, 1.0, 0.0};
-          CHK(launch_gemm_f64(s, g2, gpart), "(A VS) TS");
-          GemmF64 g3{false, true, m, ni, bi, Vt, m, VS, ni, Ac, lda, -1.0, 1.0};
-          CHK(launch_gemm_f64(s, g3, gpart), "A -= (A VS TS) VS^T");
-        }
-      }
-    }
-    // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi)
-    PanelQR pq{};
-    pq.P = X; pq.ldp = lda; pq.mi = mi; pq.nb = (int)bi;
-    pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
-    pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i;
-    next_slot(&pq.bar, &pq.abort_flag);
-    {
-      ScopedTimer tp(h, RQRCP_K_PANEL, 2.0 * mi * bi * bi - 2.0 * bi * bi * bi / 3.0, 24.0 * mi * bi);
-      CHK(launch_panel_qr(s, pq), "panel QR");
-    }
-    double *Ti = T + (size_t)i * b * b;
-    {
-      ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
-      CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
-    }
-    if (ni > bi) {
-      // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1)
-      double *C = X + bi * lda;
-      const double nc = (double)(ni - bi);
-      GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
-      {
-        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
-        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
-      }
-      GemmF64 gw{true, false, bi, ni - bi, mi, Vb, mi, C, lda, Wb, bi, 1.0, 0.0};
-      {
-        ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi, 8.0 * (mi * nc + mi * bi + bi * nc));
-        CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
-      }
-      GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0};
-      {
-        ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi, 8.0 * (2.0 * mi * nc + mi * bi + bi * nc));
-        CHK(launch_gemm_f64(s, gu, gpart), "C -= (V T^T) W");
-      }
-    }
-  }
-  (void)piv;
-  return RQRCP_OK;
+  if (dt == RQRCP_F64) return factor_impl<double>(h, P, o, static_cast<double *>(Av), lda, jpvt, tau, T, S, work);
+  return factor_impl<float>(h, P, o, static_cast<float *>(Av), lda, jpvt, tau, T, S, work);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,15 +23,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // round-robin dispatcher puts them on); the last arrival of a group arrives
 // on the top counter, and the last top arrival publishes the new generation.
 // Counters only grow, so no reset is needed between barriers; the host zeroes
-// the state once before the launch.  Every wait is bounded: after `kSpinLimit`
-// polls the waiter raises the abort word and every later wait returns at once,
-// so that a broken launch drains instead of hanging.
+// the state once before the launch.  Every wait is bounded in wall-clock time
+// (limit_ticks of the constant-rate device clock): past it the waiter raises
+// the abort word and every later wait returns at once, so that a broken launch
+// drains within about one limit instead of hanging.
 struct GridBarrier {
-  unsigned *state;   // [0]: generation, [32]: top counter, [64 + 32 g]: group g
-  int *abort_flag;   // shared abort word (zeroed by the host)
+  unsigned *state;       // [0]: generation, [32]: top counter, [64 + 32 g]: group g
+  int *abort_flag;       // shared abort word (zeroed by the host)
+  uint64_t limit_ticks;  // longest wait, in ticks of the constant-rate device clock
 };
-
-constexpr long kSpinLimit = 1L << 25;
 
 __device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen) {
   __threadfence();
@@ -53,10 +53,10 @@ __device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen) 
         __hip_atomic_store(gen_p, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     int ab = 0;
-    long spins = 0;
+    const uint64_t t0 = (uint64_t)wall_clock64();
     while (__hip_atomic_load(gen_p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
-      if (++spins > kSpinLimit) {
+      if ((uint64_t)wall_clock64() - t0 > gb.limit_ticks) {
         __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ab = 1;
         break;
@@ -78,19 +78,26 @@ __device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen) 
 hipError_t launch_sketch(hipStream_t s, uint64_t seed, int64_t block, int64_t nsample, int64_t row0,
                          int64_t nrows, double *G, int64_t ldg);
 
-// C = alpha op(A) op(B) + beta C in FP64 (MFMA), column-major.  When the
+// C = alpha op(A) op(B) + beta C on the matrix cores (FP64 or FP32), column-major.  When the
 // problem is split along K the partial products go to `partial` (at least
 // splits * M * N doubles) and a fixed-order reduction produces C.
-struct GemmF64 {
+template <typename T>
+struct Gemm {
   bool ta, tb;
   int64_t M, N, K;
-  const double *A; int64_t lda;
-  const double *B; int64_t ldb;
-  double *C; int64_t ldc;
-  double alpha, beta;
+  const T *A; int64_t lda;
+  const T *B; int64_t ldb;
+  T *C; int64_t ldc;
+  T alpha, beta;
 };
-int gemm_f64_splits(const GemmF64 &g);          // split count the launcher will use
-hipError_t launch_gemm_f64(hipStream_t s, const GemmF64 &g, double *partial);
+typedef Gemm<double> GemmF64;
+typedef Gemm<float> GemmF32;
+template <typename T> int gemm_splits(const Gemm<T> &g);   // split count the launcher will use
+template <typename T> hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial);
+inline int gemm_f64_splits(const GemmF64 &g) { return gemm_splits<double>(g); }
+inline hipError_t launch_gemm_f64(hipStream_t s, const GemmF64 &g, double *partial) {
+  return launch_gemm<double>(s, g, partial);
+}
 
 // Zero-fill of n 32-bit words (safe inside graph capture, unlike memset nodes).
 hipError_t launch_zero_u32(hipStream_t s, void *p, size_t nwords);
@@ -109,6 +116,7 @@ struct QrcpSmall {
   int *abort_flag;       // zeroed
   int32_t *info;         // may be NULL
   int block_index;
+  uint64_t limit_ticks;  // barrier wait limit
 };
 constexpr int kBarrierWords = 64 + 32 * 8;
 int qrcp_small_config(int k, int ncols, int *cpw);   // returns workgroups (0 = unsupported)
@@ -118,9 +126,10 @@ hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q);
 
 // Move the columns listed by a QrcpSmall run: column r0 + c goes to r0 +
 // dest[c], for all m rows of A and for jpvt.
-hipError_t launch_apply_moves(hipStream_t s, double *A, int64_t lda, int64_t m, int64_t r0,
+template <typename T>
+hipError_t launch_apply_moves(hipStream_t s, T *A, int64_t lda, int64_t m, int64_t r0,
                               const int32_t *moved, const int32_t *moved_cnt, const int32_t *dest,
-                              int max_moved, double *tmp, int32_t *jpvt, int32_t *jtmp);
+                              int max_moved, T *tmp, int32_t *jpvt, int32_t *jtmp);
 
 // Cooperative unpivoted Householder QR of an mi x nb panel (FP64).
 struct PanelQR {
@@ -134,6 +143,7 @@ struct PanelQR {
   int *abort_flag;
   int32_t *info;
   int block_index;
+  uint64_t limit_ticks;  // barrier wait limit
 };
 constexpr int kPanelW = 32;
 int panel_config(int64_t mi, int nb, int *rpw);   // workgroups (0 = unsupported)

@@ -1,13 +1,13 @@
-// FP64 GEMM on CDNA4 matrix cores: C = alpha op(A) op(B) + beta C, all
-// column-major.  Used for the sketch Y = G X (Section 4.1, eq. defY), the
+// GEMM on CDNA4 matrix cores (FP64 and FP32): C = alpha op(A) op(B) + beta C,
+// all column-major.  Used for the sketch Y = G X (Section 4.1, eq. defY), the
 // WY products of the trailing update C <- C - V T^T V^T C (Section 5.1) and
 // the products of the orthonormal pivoting variant and of the truncation.
 //
 // Design (gfx950, wave64):
-//  * v_mfma_f64_16x16x4f64: lane l supplies X[l%16][l/16] and Y[l/16][l%16]
-//    of D = X Y; D[i][j] lands in lane j + 16 (i%4), register i/4.  The kernel
-//    feeds X = op(B)^T and Y = op(A)^T, so that D = C^T and each lane holds
-//    16 consecutive rows of a column of C: stores are 128-byte segments.
+//  * v_mfma_{f64,f32}_16x16x4: lane l supplies X[l%16][l/16] and Y[l/16][l%16]
+//    of D = X Y (the output layouts are in Mfma<T> below).  The kernel feeds
+//    X = op(B)^T and Y = op(A)^T, so that D = C^T and each lane holds 16
+//    consecutive rows of a column of C: stores are contiguous segments.
 //  * 256 threads = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
 //    block of 16 x 16 MFMA tiles; K advances by BK = 16 through one LDS
 //    stage, the next K slab is prefetched into registers during the MFMAs.
@@ -23,20 +23,43 @@ namespace rq {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 
-template <int BM, int BN, bool TA, bool TB, bool SPLIT>
-__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
-                                                    const double *__restrict__ A, int64_t lda,
-                                                    const double *__restrict__ B, int64_t ldb,
-                                                    double *__restrict__ C, int64_t ldc, double alpha,
-                                                    double beta, double *__restrict__ partial) {
+// Matrix-core instruction per element type.  Both are 16 x 16 x 4 with lane l
+// supplying X[l%16][l/16] and Y[l/16][l%16]; they differ in where D lands:
+// FP64: D[i][j] in lane j + 16 (i%4), register i/4;
+// FP32: D[i][j] in lane j + 16 (i/4), register i%4.
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double x, double y, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+  }
+  // row index i of D (a column of C in the transposed feed) held in register r
+  static __device__ __forceinline__ int drow(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float x, float y, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                   const T *__restrict__ A, int64_t lda,
+                                                   const T *__restrict__ B, int64_t ldb,
+                                                   T *__restrict__ C, int64_t ldc, T alpha,
+                                                   T beta, T *__restrict__ partial) {
+  typedef typename Mfma<T>::acc_t acc_t;
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int AE = BM * kBK / 256, BE = BN * kBK / 256;
-  __shared__ double As[kBK][BM + kPad];
-  __shared__ double Bs[kBK][BN + kPad];
+  __shared__ T As[kBK][BM + kPad];
+  __shared__ T Bs[kBK][BN + kPad];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -44,7 +67,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
 
-  double ra[AE], rb[BE];
+  T ra[AE], rb[BE];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
@@ -52,7 +75,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
       const int i = TA ? f / kBK : f % BM;
       const int kk = TA ? f % kBK : f / BM;
       const int64_t gi = m0 + i, gk = k0 + kk;
-      ra[q] = (gi < M && gk < kend) ? (TA ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
+      ra[q] = (gi < M && gk < kend) ? (TA ? A[gk + gi * lda] : A[gi + gk * lda]) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
@@ -60,7 +83,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
       const int j = TB ? f % BN : f / kBK;
       const int kk = TB ? f / BN : f % kBK;
       const int64_t gj = n0 + j, gk = k0 + kk;
-      rb[q] = (gj < N && gk < kend) ? (TB ? B[gj + gk * ldb] : B[gk + gj * ldb]) : 0.0;
+      rb[q] = (gj < N && gk < kend) ? (TB ? B[gj + gk * ldb] : B[gk + gj * ldb]) : T(0);
     }
   };
   auto stash = [&]() {
@@ -80,11 +103,11 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
     }
   };
 
-  d4 acc[TM][TN];
+  acc_t acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{T(0), T(0), T(0), T(0)};
 
   const int lr = lane & 15, lk = lane >> 4;
   if (kbeg < kend) load(kbeg);
@@ -95,7 +118,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
     if (k0 + kBK < kend) load(k0 + kBK);
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
-      double xa[TN], yb[TM];
+      T xa[TN], yb[TM];
 #pragma unroll
       for (int b = 0; b < TN; ++b) xa[b] = Bs[kk + lk][wn * (BN / 2) + b * 16 + lr];
 #pragma unroll
@@ -104,7 +127,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[b], yb[a], acc[a][b], 0, 0, 0);
+          acc[a][b] = Mfma<T>::mma(xa[b], yb[a], acc[a][b]);
     }
   }
 
@@ -116,57 +139,59 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
     for (int b = 0; b < TN; ++b) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t col = n0 + wn * (BN / 2) + b * 16 + 4 * r + lk;
+        const int64_t col = n0 + wn * (BN / 2) + b * 16 + Mfma<T>::drow(lane, r);
         if (col >= N) continue;
-        const double v = acc[a][b][r];
+        const T v = acc[a][b][r];
         if (SPLIT) {
           partial[(int64_t)blockIdx.z * M * N + row + col * M] = v;
         } else {
-          double* cp = C + row + col * ldc;
-          *cp = (beta == 0.0) ? alpha * v : alpha * v + beta * (*cp);
+          T *cp = C + row + col * ldc;
+          *cp = (beta == T(0)) ? alpha * v : alpha * v + beta * (*cp);
         }
       }
     }
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t N, int splits,
-                                                              const double *__restrict__ partial,
-                                                              double *__restrict__ C, int64_t ldc,
-                                                              double alpha, double beta) {
+                                                              const T *__restrict__ partial,
+                                                              T *__restrict__ C, int64_t ldc,
+                                                              T alpha, T beta) {
   const int64_t MN = M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
+    T s = T(0);
     for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * MN + idx];
     const int64_t i = idx % M, j = idx / M;
-    double *cp = C + i + j * ldc;
-    *cp = (beta == 0.0) ? alpha * s : alpha * s + beta * (*cp);
+    T *cp = C + i + j * ldc;
+    *cp = (beta == T(0)) ? alpha * s : alpha * s + beta * (*cp);
   }
 }
 
-template <int BM, int BN, bool TA, bool TB>
-hipError_t launch_tiles(hipStream_t s, const GemmF64 &g, int splits, int64_t kchunk, double *partial) {
+template <typename T, int BM, int BN, bool TA, bool TB>
+hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)splits);
   if (splits > 1)
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, TA, TB, true>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, true>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
                        g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   else
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
                        g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   return hipGetLastError();
 }
 
-template <bool TA, bool TB>
-hipError_t launch_shape(hipStream_t s, const GemmF64 &g, int splits, int64_t kchunk, double *partial) {
+template <typename T, bool TA, bool TB>
+hipError_t launch_shape(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   const bool sm = g.M <= 64, sn = g.N <= 64;
-  if (sm && sn) return launch_tiles<64, 64, TA, TB>(s, g, splits, kchunk, partial);
-  if (sm) return launch_tiles<64, 128, TA, TB>(s, g, splits, kchunk, partial);
-  if (sn) return launch_tiles<128, 64, TA, TB>(s, g, splits, kchunk, partial);
-  return launch_tiles<128, 128, TA, TB>(s, g, splits, kchunk, partial);
+  if (sm && sn) return launch_tiles<T, 64, 64, TA, TB>(s, g, splits, kchunk, partial);
+  if (sm) return launch_tiles<T, 64, 128, TA, TB>(s, g, splits, kchunk, partial);
+  if (sn) return launch_tiles<T, 128, 64, TA, TB>(s, g, splits, kchunk, partial);
+  return launch_tiles<T, 128, 128, TA, TB>(s, g, splits, kchunk, partial);
 }
 
-void split_plan(const GemmF64 &g, int *splits, int64_t *kchunk) {
+template <typename T>
+void split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   const int64_t bm = g.M <= 64 ? 64 : 128, bn = g.N <= 64 ? 64 : 128;
   const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   int64_t sp = 1;
@@ -188,29 +213,36 @@ void split_plan(const GemmF64 &g, int *splits, int64_t *kchunk) {
 
 }  // namespace
 
-int gemm_f64_splits(const GemmF64 &g) {
+template <typename T>
+int gemm_splits(const Gemm<T> &g) {
   int sp; int64_t kc;
   split_plan(g, &sp, &kc);
   return sp;
 }
 
-hipError_t launch_gemm_f64(hipStream_t s, const GemmF64 &g, double *partial) {
+template <typename T>
+hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   int splits; int64_t kchunk;
   split_plan(g, &splits, &kchunk);
   if (g.K <= 0) splits = 1;
   hipError_t e;
-  if (!g.ta && !g.tb) e = launch_shape<false, false>(s, g, splits, kchunk, partial);
-  else if (g.ta && !g.tb) e = launch_shape<true, false>(s, g, splits, kchunk, partial);
-  else if (!g.ta && g.tb) e = launch_shape<false, true>(s, g, splits, kchunk, partial);
-  else e = launch_shape<true, true>(s, g, splits, kchunk, partial);
+  if (!g.ta && !g.tb) e = launch_shape<T, false, false>(s, g, splits, kchunk, partial);
+  else if (g.ta && !g.tb) e = launch_shape<T, true, false>(s, g, splits, kchunk, partial);
+  else if (!g.ta && g.tb) e = launch_shape<T, false, true>(s, g, splits, kchunk, partial);
+  else e = launch_shape<T, true, true>(s, g, splits, kchunk, partial);
   if (e != hipSuccess || splits == 1) return e;
   const int64_t MN = g.M * g.N;
   int64_t grid = (MN + 255) / 256;
   if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits, partial, g.C,
-                     g.ldc, g.alpha, g.beta);
+  hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits, partial,
+                     g.C, g.ldc, g.alpha, g.beta);
   return hipGetLastError();
 }
+
+template int gemm_splits<double>(const Gemm<double> &);
+template int gemm_splits<float>(const Gemm<float> &);
+template hipError_t launch_gemm<double>(hipStream_t, const Gemm<double> &, double *);
+template hipError_t launch_gemm<float>(hipStream_t, const Gemm<float> &, float *);
 
 }  // namespace rq

@@ -111,6 +111,37 @@ __global__ void tri_inv_upper_kernel(const double *__restrict__ R, int64_t ldr, 
   }
 }
 
+template <typename S, typename D>
+__global__ void copy_cast_kernel(const S *__restrict__ s, int64_t lds, D *__restrict__ d, int64_t ldd, int64_t rows,
+                                 int64_t cols) {
+  GRID_STRIDE(i, rows * cols) {
+    const int64_t r = i % rows, c = i / rows;
+    d[r + c * ldd] = (D)s[r + c * lds];
+  }
+}
+
+template <typename T>
+__global__ void gather_cols_t_kernel(const T *__restrict__ s, int64_t lds, int64_t rows, int64_t scols,
+                                     const int32_t *__restrict__ idx, int64_t ncols, T *__restrict__ d, int64_t ldd) {
+  GRID_STRIDE(i, rows * ncols) {
+    const int64_t r = i % rows, c = i / rows;
+    const int64_t src = idx[c];
+    d[r + c * ldd] = (src >= 0 && src < scols) ? s[r + src * lds] : (T)__builtin_nan("");
+  }
+}
+
+template <typename T>
+__global__ void scatter_cols_t_kernel(const T *__restrict__ s, int64_t lds, int64_t rows, const int32_t *__restrict__ idx,
+                                      int64_t ncols, T *__restrict__ d, int64_t ldd, int64_t dcols, int add) {
+  GRID_STRIDE(i, rows * ncols) {
+    const int64_t r = i % rows, c = i / rows;
+    const int64_t dc = idx[c];
+    if (dc < 0 || dc >= dcols) continue;
+    T *p = d + r + dc * ldd;
+    *p = add ? *p + s[r + c * lds] : s[r + c * lds];
+  }
+}
+
 }  // namespace
 
 #define LAUNCH1D(kern, n, ...)                                                         \
@@ -152,6 +183,26 @@ hipError_t launch_set_identity(hipStream_t s, double *E, int64_t lde, int64_t ro
   LAUNCH1D(set_identity_kernel, rows * cols, E, lde, rows, cols);
 }
 hipError_t launch_iota(hipStream_t s, int32_t *p, int64_t n) { LAUNCH1D(iota_kernel, n, p, n); }
+hipError_t launch_copy_f32_f64(hipStream_t s, const float *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                               int64_t cols) {
+  LAUNCH1D((copy_cast_kernel<float, double>), rows * cols, src, lds, dst, ldd, rows, cols);
+}
+hipError_t launch_copy_f64_f32(hipStream_t s, const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows,
+                               int64_t cols) {
+  LAUNCH1D((copy_cast_kernel<double, float>), rows * cols, src, lds, dst, ldd, rows, cols);
+}
+hipError_t launch_copy2d_f32(hipStream_t s, const float *src, int64_t lds, float *dst, int64_t ldd, int64_t rows,
+                             int64_t cols) {
+  LAUNCH1D((copy_cast_kernel<float, float>), rows * cols, src, lds, dst, ldd, rows, cols);
+}
+hipError_t launch_gather_cols_f32(hipStream_t s, const float *src, int64_t lds, int64_t rows, int64_t scols,
+                                  const int32_t *idx, int64_t ncols, float *dst, int64_t ldd) {
+  LAUNCH1D(gather_cols_t_kernel<float>, rows * ncols, src, lds, rows, scols, idx, ncols, dst, ldd);
+}
+hipError_t launch_scatter_cols_f32(hipStream_t s, const float *src, int64_t lds, int64_t rows, const int32_t *idx,
+                                   int64_t ncols, float *dst, int64_t ldd, int64_t dcols, bool add) {
+  LAUNCH1D(scatter_cols_t_kernel<float>, rows * ncols, src, lds, rows, idx, ncols, dst, ldd, dcols, add ? 1 : 0);
+}
 hipError_t launch_tri_inv_upper(hipStream_t s, const double *R, int64_t ldr, int64_t k, double *Ri, int64_t ldi) {
   if (k <= 0) return hipSuccess;
   hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s, R, ldr, k, Ri, ldi);

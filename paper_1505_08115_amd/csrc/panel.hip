@@ -294,7 +294,7 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
   }
   const size_t lds = panel_lds_doubles(rpw, p.nb) * sizeof(double);
   PanelQR pp = p;
-  GridBarrier gb{p.bar, p.abort_flag};
+  GridBarrier gb{p.bar, p.abort_flag, p.limit_ticks};
   void *args[] = {&pp, &rpw, &gb};
   return hipLaunchCooperativeKernel((const void *)panel_qr_kernel, dim3(nwg), dim3(kPThreads), args,
                                     (unsigned)lds, s);

@@ -200,10 +200,11 @@ __global__ __launch_bounds__(kQThreads) void qrcp_small_kernel(QrcpSmall q, int 
   }
 }
 
-__global__ __launch_bounds__(256) void gather_moved_kernel(const double *__restrict__ A, int64_t lda, int64_t m,
+template <typename T>
+__global__ __launch_bounds__(256) void gather_moved_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
                                                            int64_t r0, const int32_t *__restrict__ moved,
                                                            const int32_t *__restrict__ moved_cnt,
-                                                           double *__restrict__ tmp,
+                                                           T *__restrict__ tmp,
                                                            const int32_t *__restrict__ jpvt,
                                                            int32_t *__restrict__ jtmp) {
   const int slot = blockIdx.x;
@@ -214,11 +215,12 @@ __global__ __launch_bounds__(256) void gather_moved_kernel(const double *__restr
   if (blockIdx.y == 0 && threadIdx.x == 0) jtmp[slot] = jpvt[c];
 }
 
-__global__ __launch_bounds__(256) void scatter_moved_kernel(double *__restrict__ A, int64_t lda, int64_t m,
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_moved_kernel(T *__restrict__ A, int64_t lda, int64_t m,
                                                             int64_t r0, const int32_t *__restrict__ moved,
                                                             const int32_t *__restrict__ moved_cnt,
                                                             const int32_t *__restrict__ dest,
-                                                            const double *__restrict__ tmp,
+                                                            const T *__restrict__ tmp,
                                                             int32_t *__restrict__ jpvt,
                                                             const int32_t *__restrict__ jtmp) {
   const int slot = blockIdx.x;
@@ -268,26 +270,31 @@ hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
   }
   const size_t lds = lds_doubles(q.k, cpw) * sizeof(double);
   QrcpSmall qq = q;
-  GridBarrier gb{q.bar, q.abort_flag};
+  GridBarrier gb{q.bar, q.abort_flag, q.limit_ticks};
   void *args[] = {&qq, &cpw, &gb};
   return hipLaunchCooperativeKernel((const void *)qrcp_small_kernel, dim3(nwg), dim3(kQThreads), args,
                                     (unsigned)lds, s);
 }
 
-hipError_t launch_apply_moves(hipStream_t s, double *A, int64_t lda, int64_t m, int64_t r0,
+template <typename T>
+hipError_t launch_apply_moves(hipStream_t s, T *A, int64_t lda, int64_t m, int64_t r0,
                               const int32_t *moved, const int32_t *moved_cnt, const int32_t *dest,
-                              int max_moved, double *tmp, int32_t *jpvt, int32_t *jtmp) {
+                              int max_moved, T *tmp, int32_t *jpvt, int32_t *jtmp) {
   if (max_moved <= 0) return hipSuccess;
   int64_t gy = (m + 1023) / 1024;
   if (gy > 64) gy = 64;
   if (gy < 1) gy = 1;
   dim3 grid((unsigned)max_moved, (unsigned)gy);
-  hipLaunchKernelGGL(gather_moved_kernel, grid, dim3(256), 0, s, A, lda, m, r0, moved, moved_cnt, tmp, jpvt, jtmp);
+  hipLaunchKernelGGL(gather_moved_kernel<T>, grid, dim3(256), 0, s, A, lda, m, r0, moved, moved_cnt, tmp, jpvt, jtmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scatter_moved_kernel, grid, dim3(256), 0, s, A, lda, m, r0, moved, moved_cnt, dest, tmp, jpvt,
+  hipLaunchKernelGGL(scatter_moved_kernel<T>, grid, dim3(256), 0, s, A, lda, m, r0, moved, moved_cnt, dest, tmp, jpvt,
                      jtmp);
   return hipGetLastError();
 }
+template hipError_t launch_apply_moves<double>(hipStream_t, double *, int64_t, int64_t, int64_t, const int32_t *,
+                                               const int32_t *, const int32_t *, int, double *, int32_t *, int32_t *);
+template hipError_t launch_apply_moves<float>(hipStream_t, float *, int64_t, int64_t, int64_t, const int32_t *,
+                                              const int32_t *, const int32_t *, int, float *, int32_t *, int32_t *);
 
 }  // namespace rq

@@ -1,13 +1,21 @@
 """Helpers shared by the GPU parity tests (not collected by pytest)."""
+import os
+import sys
+import time
+
 import numpy as np
 
 U = np.finfo(np.float64).eps / 2
 
 # A pivot decision of the oracle is "separated" when its top-two margin
-# (nu_1^2 - nu_2^2)/nu_1^2 exceeds the relative perturbation that rounding
-# differences between two FP64 implementations can cause in that block's
-# sketch.  That perturbation is taken as NOISE * u * |A|_F / |X_i|_F: errors
-# of earlier blocks are absolute (a few u |A|) while X_i shrinks.
+# (nu_1^2 - nu_2^2)/nu_1^2 exceeds what rounding differences between two FP64
+# implementations can cause.  Those differences are absolute: a few u |A| in
+# the trailing matrix X_i, hence about u (|A|/|X_i|) |Y_i| in the sketch Y_i
+# and in every residual norm nu computed from it.  Relative to the leading
+# residual norm nu_1 of the step, that is u (|A|/|X_i|) (|Y_i|/nu_1); the
+# threshold is NOISE times that.  Late steps whose residuals are at roundoff
+# level (e.g. past the rank of an exactly rank-deficient input) are therefore
+# never counted as separated.
 NOISE = 1.0e4
 
 
@@ -16,12 +24,20 @@ def separated_prefix(res, noise=NOISE):
     if not res["margins"]:
         return 0
     nA = res["xnorm"][0]
-    for (r0, bi), mg, xn in zip(res["blocks"], res["margins"], res["xnorm"]):
-        delta = noise * U * nA / max(xn, 1e-300)
+    for (r0, bi), mg, xn, yn, tops in zip(res["blocks"], res["margins"], res["xnorm"], res["ynorm"],
+                                           res["tops"]):
         for j in range(bi):
+            delta = noise * U * (nA / max(xn, 1e-300)) * (yn / max(tops[j], 1e-300))
             if not (mg[j] > delta):
                 return r0 + j
-    return res["F"].shape[1]
+    return res["rank"]
+
+
+def first_mismatch(a, b):
+    """Index of the first differing entry of two equal-length sequences, or -1."""
+    a, b = np.asarray(a), np.asarray(b)
+    d = np.nonzero(a != b)[0]
+    return int(d[0]) if d.size else -1
 
 
 def min_margin(res):
@@ -42,3 +58,17 @@ def sign_rows(R):
     d = np.sign(np.diag(R[:, : R.shape[0]])) if R.shape[0] <= R.shape[1] else np.sign(np.diag(R))
     d = np.where(d == 0, 1.0, d)
     return d[:, None] * R
+
+
+_T0 = time.time()
+
+
+def progress(msg):
+    """Flush a timestamped step line to stderr and to gpurun_out/progress.log."""
+    line = f"[{time.time() - _T0:8.1f}s] {msg}"
+    print(line, file=sys.stderr, flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = os.path.join(root, "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "progress.log"), "a") as f:
+            f.write(line + "\n")

@@ -19,7 +19,7 @@ import paper_1505_08115_amd as R
 import workloads as W
 from oracle import philox
 from oracle import rqrcp as O
-from tests.parity import r_times_pt, separated_prefix, sign_rows
+from tests.parity import first_mismatch, progress, r_times_pt, separated_prefix, sign_rows
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -63,7 +63,7 @@ def _invariants(A_np, Fz, tol_res=1e-13, tol_orth=1e-12):
     assert float(res) <= tol_res, f"residual {float(res):.3e}"
     assert float(orth) <= tol_orth, f"orthogonality {float(orth):.3e}"
     if Fz.pivot == "perm":
-        assert sorted(Fz.jpvt.cpu().tolist()) == list(range(n))
+        assert np.array_equal(np.sort(Fz.jpvt.cpu().numpy()), np.arange(n)), "jpvt is not a permutation"
     return float(res), float(orth)
 
 
@@ -72,7 +72,8 @@ def _compare(A_np, Fz, ref, expect_prefix=None):
     pre = separated_prefix(ref)
     jg = Fz.jpvt.cpu().numpy()
     if Fz.pivot == "perm":
-        assert list(jg[:pre]) == list(ref["jpvt"][:pre]), f"pivots differ before position {pre}"
+        bad = first_mismatch(jg[:pre], ref["jpvt"][:pre])
+        assert bad < 0, f"pivots differ at position {bad} (separated prefix {pre})"
     else:
         pre = ref["rank"]
     if expect_prefix is not None:
@@ -153,7 +154,7 @@ def test_C1_full_parity():
     assert info.cpu().tolist() == [0, 0, 0, 0]
     pre = _compare(A, Fz, ref)
     assert pre == w.n, f"C1 should be fully separated, prefix {pre}"
-    assert list(Fz.jpvt.cpu().numpy()) == list(ref["jpvt"])
+    assert first_mismatch(Fz.jpvt.cpu().numpy(), ref["jpvt"]) < 0
     _invariants(A, Fz)
     # R and T blocks match the oracle everywhere (same pivots)
     np.testing.assert_allclose(sign_rows(np.triu(Fz.F.cpu().numpy())), sign_rows(np.triu(ref["F"])), rtol=0,
@@ -199,14 +200,24 @@ def test_nonfinite_input_raises_the_info_flag():
 @pytest.mark.parametrize("name", ["C2", "C2r"])
 def test_C2_parity_and_exact_rank(name):
     w = W.WORKLOADS[name]
+    progress(f"{name}: generating the input on the GPU")
     A_dev = W.workload_matrix(w, device=DEV)
     A = A_dev.cpu().numpy()
-    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed)
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    progress(f"{name}: GPU factorization")
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed, info=info)
     torch.cuda.synchronize()
-    ref = O.rqrcp(A, w.b, w.p, seed=w.seed)
+    progress(f"{name}: GPU done, info {info.tolist()}; oracle")
+    assert info.cpu().tolist()[2] == 0, "a grid barrier gave up"
+    # the oracle stops at rank 1024 for the rank-1000 input: its later
+    # decisions are among noise columns and cannot be separated
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed, rank=1024 if name == "C2r" else 0)
+    progress(f"{name}: oracle done; comparing")
     pre = _compare(A, Fz, ref)
     assert pre >= 512, f"separated prefix only {pre}"
+    progress(f"{name}: separated prefix {pre}; invariants")
     _invariants(A, Fz)
+    progress(f"{name}: invariants ok")
     if name == "C2r":
         Rg = np.triu(Fz.F.cpu().numpy())
         tail = np.linalg.norm(Rg[1000:, 1000:])
@@ -221,7 +232,9 @@ def test_C3_subcase_ortho_tracks_singular_values():
     torch.cuda.synchronize()
     _compare(A, Fz, ref)
     _invariants(A, Fz)
-    sv = O.jacobi_singular_values(A)
+    # singular values from LAPACK (the oracle's Jacobi SVD is pinned to it on
+    # small sizes; at 1024 its pure-numpy sweeps take minutes)
+    sv = np.linalg.svd(A, compute_uv=False)
     dg = np.abs(np.diag(Fz.F.cpu().numpy()))
     do = np.abs(np.diag(ref["F"]))
     # |R_ii| of the GPU factorization tracks the oracle's relative to sigma_i
@@ -235,9 +248,14 @@ def test_H1_full_size_properties_and_first_block_pivots():
     """n = 8192 in the benchmark's configuration: invariants at full size,
     and the first block's pivots against the oracle's sketch and QRCP."""
     w = W.WORKLOADS["H1"]
+    progress("H1: generating the input on the GPU")
     A_dev = W.workload_matrix(w, device=DEV)
-    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed)
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    progress("H1: GPU factorization")
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed, info=info)
     torch.cuda.synchronize()
+    progress(f"H1: GPU done, info {info.tolist()}")
+    assert info.cpu().tolist() == [0, 0, 0, 0]
     m, n = A_dev.shape
     _invariants(A_dev.cpu().numpy(), Fz, tol_res=1e-12, tol_orth=1e-11)
     A = A_dev.cpu().numpy()
@@ -246,7 +264,7 @@ def test_H1_full_size_properties_and_first_block_pivots():
     piv, jp, _, mg = O.qrcp(Y, steps=w.b, record_margins=True)
     sep = int(np.argmax(~(mg > 1e-10))) if np.any(~(mg > 1e-10)) else w.b
     assert sep >= 200
-    assert list(Fz.jpvt.cpu().numpy()[:sep]) == list(jp[:sep])
+    assert first_mismatch(Fz.jpvt.cpu().numpy()[:sep], jp[:sep]) < 0
 
 
 def test_apply_q_apply_p_lowrank_match_oracle():
@@ -282,3 +300,74 @@ def test_lowrank_backward_matches_oracle_gradient(m, n, k, b):
     dA = R.lowrank_backward(R.colmajor(torch.tensor(A, device=DEV)), Fz, R.colmajor(Gbar), k).cpu().numpy()
     ref = O.lowrank_grad(A, jp, k, Gbar.cpu().numpy())
     np.testing.assert_allclose(dA, ref, atol=1e-10 * np.abs(ref).max())
+
+
+def _f32_checks(A32, Fz, tol_res=1e-5, tol_orth=1e-4):
+    """Invariants of an FP32-storage factorization, evaluated in FP64 against
+    the FP32-rounded input (the matrix the factorization actually saw)."""
+    A = torch.tensor(A32.astype(np.float64), device=DEV)
+    F = Fz.F.double()
+    k = Fz.rank
+    n = A.shape[1]
+    Q = torch.linalg.householder_product(F[:, :k].contiguous(), Fz.tau[:k].contiguous())
+    AP = A[:, Fz.jpvt.long()]
+    res = float(torch.linalg.norm(AP - Q @ torch.triu(F[:k, :])) / torch.linalg.norm(A))
+    orth = float(torch.linalg.norm(Q.T @ Q - torch.eye(k, device=DEV, dtype=torch.float64)))
+    assert np.array_equal(np.sort(Fz.jpvt.cpu().numpy()), np.arange(n)), "jpvt is not a permutation"
+    assert res <= tol_res, f"residual {res:.3e}"
+    assert orth <= tol_orth, f"orthogonality {orth:.3e}"
+    return res, orth
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+@pytest.mark.parametrize("m,n,b,p", [(300, 250, 32, 8), (512, 512, 32, 8), (1024, 768, 128, 16)])
+def test_fp32_storage_error_bounds(precision, m, n, b, p):
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 6.0), seed=m + n).numpy()
+    A32 = A.astype(np.float32)
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=p, seed=5, precision=precision, info=info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 0, 0, 0]
+    res, orth = _f32_checks(A32, Fz)
+    # pivot agreement with the FP64 oracle on the same FP32-rounded input: reported, not binding
+    ref = O.rqrcp(A32.astype(np.float64), b, p, seed=5)
+    agree = first_mismatch(Fz.jpvt.cpu().numpy(), ref["jpvt"])
+    progress(f"fp32 {precision} {m}x{n}: residual {res:.2e} orth {orth:.2e} "
+             f"pivots agree up to {agree if agree >= 0 else n}")
+    # the leading decisions are far apart in these inputs: the first block agrees
+    assert agree < 0 or agree >= b // 2
+
+
+def test_fp32_ortho_and_truncated():
+    m, n, b, p = 400, 320, 32, 8
+    A32 = W.make_matrix(m, n, W.sigma_geometric(n, 5.0), seed=2).numpy().astype(np.float32)
+    for pivot, rank in (("ortho", 0), ("perm", 96)):
+        Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=p, seed=3, precision="mixed",
+                      pivot=pivot, rank=rank)
+        torch.cuda.synchronize()
+        A = torch.tensor(A32.astype(np.float64), device=DEV)
+        F = Fz.F.double()
+        k = Fz.rank
+        Q = torch.linalg.householder_product(F[:, :k].contiguous(), Fz.tau[:k].contiguous())
+        if pivot == "perm":
+            res = torch.linalg.norm(Q.T @ A[:, Fz.jpvt.long()] - torch.triu(F[:k, :])) / torch.linalg.norm(A)
+        else:
+            # P from the stored S blocks (FP64) applied by the oracle's definition
+            S = Fz.S.cpu().numpy()
+            nb = -(-n // b)
+            P = np.eye(n)
+            off = 0
+            offs = []
+            for i in range(nb):
+                offs.append(off)
+                off += (n - i * b) * b
+            TS0 = off + nb * b
+            for i in range(nb):
+                r0, bi = i * b, min(b, n - i * b)
+                VS = S[offs[i]: offs[i] + (n - r0) * b].reshape(b, n - r0).T[:, :bi]
+                TS = S[TS0 + i * b * b: TS0 + (i + 1) * b * b].reshape(b, b).T[:bi, :bi]
+                Pc = P[:, r0:]
+                Pc -= ((Pc @ VS) @ TS) @ VS.T
+            AP = torch.tensor(A32.astype(np.float64) @ P, device=DEV)
+            res = torch.linalg.norm(AP - Q @ torch.triu(F[:k, :])) / torch.linalg.norm(A)
+        assert float(res) <= 1e-5, f"{pivot}: residual {float(res):.3e}"
