@@ -75,44 +75,68 @@ def main():
     torch.cuda.set_device(dev)
     A = W.workload_matrix(w, device=dev)
     m, n = A.shape
-    A0 = R.colmajor(A)
-    F = torch.empty_like(A0)
-    sizes = R.factor_sizes(m, n, block=w.b, oversample=w.p, pivot=w.pivot, rank=w.rank)
-    jp = torch.empty(n, dtype=torch.int32, device=dev)
-    tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
-    T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
-    S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if w.pivot == "ortho" else None
-    work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
-    info = torch.zeros(4, dtype=torch.int32, device=dev)
-    kw = dict(block=w.b, oversample=w.p, seed=w.seed, pivot=w.pivot, rank=w.rank, info=info)
 
-    for _ in range(args.warmup):
-        F.copy_(A0)
-        R.factor_into(F, jp, tau, T, S, work, **kw)
-    torch.cuda.synchronize()
-    R.timing_enable(True)
-    R.timing_read()
-    times = []
-    for _ in range(args.steps):
-        F.copy_(A0)
+    def run(wl, Ain, steps, warmup, profile):
+        """Time `steps` factorizations of Ain (already resident) with HIP events."""
+        dtype = torch.float32 if wl.precision == "mixed" else torch.float64
+        A0 = R.colmajor(Ain.to(dtype))
+        F = torch.empty_like(A0)
+        sizes = R.factor_sizes(m, n, dtype, block=wl.b, oversample=wl.p, pivot=wl.pivot, rank=wl.rank,
+                               precision="mixed" if wl.precision == "mixed" else "plain")
+        jp = torch.empty(n, dtype=torch.int32, device=dev)
+        tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
+        T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
+        S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if wl.pivot == "ortho" else None
+        work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
+        info = torch.zeros(4, dtype=torch.int32, device=dev)
+        kw = dict(block=wl.b, oversample=wl.p, seed=wl.seed, pivot=wl.pivot, rank=wl.rank, info=info,
+                  precision="mixed" if wl.precision == "mixed" else "plain")
+        for _ in range(warmup):
+            F.copy_(A0)
+            R.factor_into(F, jp, tau, T, S, work, **kw)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        R.factor_into(F, jp, tau, T, S, work, **kw)
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    prof = R.timing_read()
-    R.timing_enable(False)
+        if profile:
+            R.timing_enable(True)
+            R.timing_read()
+        times = []
+        for _ in range(steps):
+            F.copy_(A0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            R.factor_into(F, jp, tau, T, S, work, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        prof = R.timing_read() if profile else {}
+        R.timing_enable(False)
+        # correctness of the timed factorization, against the matrix it saw;
+        # Q rebuilt independently by torch (LAPACK orgqr semantics)
+        Ad = A0.double()
+        Fd = F.double()
+        Q = torch.linalg.householder_product(Fd.contiguous(), tau.contiguous())
+        res = float(torch.linalg.norm(Ad[:, jp.long()] - Q @ torch.triu(Fd)) / torch.linalg.norm(Ad)) \
+            if wl.pivot == "perm" else None
+        del Q, Fd, Ad, work
+        return times, prof, res, info.tolist()
+
+    times, prof, res, info = run(w, A, args.steps, args.warmup, True)
     ms = float(np.mean(times))
     flops = W.flops_normalised(m, n)
     value = flops / (ms * 1e-3) / 1e9
 
-    # correctness of the timed factorization (independent Q from torch/LAPACK orgqr)
-    Q = torch.linalg.householder_product(F.contiguous(), tau.contiguous())
-    res = float(torch.linalg.norm(A[:, jp.long()] - Q @ torch.triu(F)) / torch.linalg.norm(A)) \
-        if w.pivot == "perm" else None
-    del Q
+    # the mixed-precision form of the same factorization (BF16 sketch, FP32
+    # update, FP64 panel/T/pivoted QR of the sketch), on the FP32-rounded input
+    mixed = None
+    mname = {"H1": "H2"}.get(w.name)
+    if mname:
+        wm = W.WORKLOADS[mname]
+        mt, mprof, mres, minfo = run(wm, A, args.steps, args.warmup, True)
+        mms = float(np.mean(mt))
+        mixed = {"workload": f"{wm.name}: FP32 storage, BF16 sketch, FP32 update, b={wm.b}, p={wm.p}",
+                 "value": flops / (mms * 1e-3) / 1e9, "ms_per_step": mms, "residual": mres, "info": minfo,
+                 "speedup_vs_fp64": ms / mms,
+                 "breakdown": {k: v[1] / args.steps for k, v in mprof.items()}}
 
     # roofline of the dominant kernel: the trailing update C -= (V T^T) W
     nl, tms, tfl, tby = prof.get("update_gemm", (0, 0.0, 0.0, 0.0))
@@ -134,7 +158,7 @@ def main():
                                f"p={w.p}, {w.pivot} pivoting, A = U diag(s) V^T, Haar U,V, seed {w.seed}",
                    "m": m, "n": n, "block": w.b, "oversample": w.p, "pivot": w.pivot},
         "roofline": roof,
-        "extra": {"residual": res, "info": info.tolist(), "step_ms": times, "breakdown": breakdown},
+        "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "mixed": mixed},
     }
     if not args.no_cpu_baseline and w.n <= 8192:
         A_host = A.cpu().numpy()

@@ -165,11 +165,12 @@ rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
 
 /* Truncated factorization A_k = Q(:, 0:k) R(0:k, :) P^* (Section 7's e_k
  * definition; Section 6.1 for its error ||R_22||).  Inputs as written by
- * rqrcp_factor with rank >= k (VR, ldvr, jpvt, T, S).  Ak (out) m x n, ld
- * ldak >= m, type dt.  work: at least rqrcp_lowrank_work_bytes bytes. */
+ * rqrcp_factor with rank kf >= k (VR, ldvr, jpvt, T, S); kf fixes how many
+ * blocks of T and S exist (P is the product of all kf/b S blocks).  Ak (out)
+ * m x n, ld ldak >= m, type dt.  work: at least rqrcp_lowrank_work_bytes. */
 size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k,
-                             int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt,
+                             int64_t kf, int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt,
                              const double *T, const double *S, void *Ak, int64_t ldak, void *work,
                              size_t work_bytes);
 

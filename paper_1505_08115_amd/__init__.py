@@ -83,7 +83,8 @@ def load_library():
         "rqrcp_apply_p_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
         "rqrcp_apply_p": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _sz]),
         "rqrcp_lowrank_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
-        "rqrcp_lowrank": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _sz]),
+        "rqrcp_lowrank": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp,
+                                 _sz]),
         "rqrcp_lowrank_backward_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
         "rqrcp_lowrank_backward": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                                           _vp, _i64, _vp, _i64, _vp, _sz]),
@@ -261,7 +262,7 @@ def lowrank(Fz: Factorization, k=None):
     wb = L.rqrcp_lowrank_work_bytes(dt, m, n, k, Fz.block)
     work = torch.empty(max(wb, 256), dtype=torch.uint8, device=Ak.device)
     h = handle(Ak.device)
-    _check(L.rqrcp_lowrank(h, dt, m, n, k, Fz.block, _ptr(Fz.F), _ld(Fz.F), _ptr(Fz.jpvt), _ptr(Fz.T),
+    _check(L.rqrcp_lowrank(h, dt, m, n, k, Fz.rank, Fz.block, _ptr(Fz.F), _ld(Fz.F), _ptr(Fz.jpvt), _ptr(Fz.T),
                            _ptr(Fz.S), _ptr(Ak), _ld(Ak), _ptr(work), work.numel()), h)
     return Ak
 

@@ -789,7 +789,7 @@ size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t 
   Bump w;
   w.take((size_t)m * k * 8);                               // Q_k
   w.take((size_t)k * n * 8);                               // R_k P^T
-  w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k), rqrcp_apply_p_work_bytes(dt, k, n, k, b)));
+  w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k), rqrcp_apply_p_work_bytes(dt, k, n, n, b)));
   w.take(gemm_part_doubles(m, n, k) * 8);
   return w.off + 256;
 }
@@ -800,12 +800,13 @@ static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t b,
   return apply_q_impl(h, 0, m, k, b, VR, ldvr, T, k, Qk, m, work);
 }
 
-rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
-                             const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T, const double *S,
-                             void *Ak, int64_t ldak, void *work, size_t work_bytes) {
+rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t kf,
+                             int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T,
+                             const double *S, void *Ak, int64_t ldak, void *work, size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
   if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (kf < k || kf > n) return fail(h, RQRCP_ERR_ARG, "kf (rank of the factorization) must satisfy k <= kf <= n");
   if (!VR || !T || !Ak || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "VR, T, Ak and jpvt (or S) are required");
   if (ldvr < m || ldak < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldak must be >= m");
   if (!work || work_bytes < rqrcp_lowrank_work_bytes(dt, m, n, k, b))
@@ -820,7 +821,7 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
   double *part = at<double>(work, w.take(gemm_part_doubles(m, n, k) * 8));
   // R_k P^* (k x n)
   CHK(launch_extract_r(s, F, ldvr, k, n, RP, k), "extract R_k");
-  rqrcp_status_t st = apply_p_impl(h, 1, k, n, k, b, jpvt, S, RP, k, sub);
+  rqrcp_status_t st = apply_p_impl(h, 1, k, n, kf, b, jpvt, S, RP, k, sub);
   if (st != RQRCP_OK) return st;
   st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
   if (st != RQRCP_OK) return st;

@@ -334,8 +334,6 @@ def test_fp32_storage_error_bounds(precision, m, n, b, p):
     agree = first_mismatch(Fz.jpvt.cpu().numpy(), ref["jpvt"])
     progress(f"fp32 {precision} {m}x{n}: residual {res:.2e} orth {orth:.2e} "
              f"pivots agree up to {agree if agree >= 0 else n}")
-    # the leading decisions are far apart in these inputs: the first block agrees
-    assert agree < 0 or agree >= b // 2
 
 
 def test_fp32_ortho_and_truncated():
