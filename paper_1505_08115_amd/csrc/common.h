@@ -18,57 +18,71 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Grid-wide barrier for cooperatively launched kernels.  Workgroups arrive on
-// one of 8 group counters (grouped by blockIdx % 8, i.e. by the XCD that the
-// round-robin dispatcher puts them on); the last arrival of a group arrives
-// on the top counter, and the last top arrival publishes the new generation.
-// Counters only grow, so no reset is needed between barriers; the host zeroes
-// the state once before the launch.  Every wait is bounded in wall-clock time
-// (limit_ticks of the constant-rate device clock): past it the waiter raises
-// the abort word and every later wait returns at once, so that a broken launch
-// drains within about one limit instead of hanging.
+// Grid-wide barrier for cooperatively launched kernels, called by ONE thread
+// of the workgroup (the caller brackets it with __syncthreads).  Workgroups
+// arrive on one of 8 group counters (grouped by blockIdx % 8, i.e. by the XCD
+// that the round-robin dispatcher puts them on); the last arrival of a group
+// arrives on the top counter, and the last top arrival publishes the new
+// generation.  Counters only grow, so no reset is needed between barriers; the
+// host zeroes the state once before the launch.
+//
+// Memory ordering: arrivals are release operations (they publish the calling
+// wave's earlier writes), a group's last arrival and the top's last arrival
+// acquire before passing the arrivals on, and waiters poll with relaxed loads
+// and acquire once when the generation has moved.  Data that other
+// workgroups must see is therefore written by the wave that calls this
+// function; after it returns and the workgroup has passed a __syncthreads,
+// every wave of the workgroup may read data published by the others.
+//
+// Every wait is bounded in wall-clock time (limit_ticks of the constant-rate
+// device clock): past it the waiter raises the abort word and every later wait
+// returns at once, so that a broken launch drains within about one limit.
 struct GridBarrier {
   unsigned *state;       // [0]: generation, [32]: top counter, [64 + 32 g]: group g
   int *abort_flag;       // shared abort word (zeroed by the host)
   uint64_t limit_ticks;  // longest wait, in ticks of the constant-rate device clock
 };
 
-__device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen) {
-  __threadfence();
-  __syncthreads();
-  __shared__ int s_abort;
-  if (threadIdx.x == 0) {
-    const unsigned nwg = gridDim.x;
-    const unsigned ngroups = nwg < 8 ? nwg : 8;
-    const unsigned g = blockIdx.x % ngroups;
-    const unsigned gsize = (nwg - g + ngroups - 1) / ngroups;
-    unsigned *gen_p = gb.state;
-    unsigned *top_p = gb.state + 32;
-    unsigned *grp_p = gb.state + 64 + 32 * g;
-    const unsigned target = gen + 1;
-    unsigned old = __hip_atomic_fetch_add(grp_p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 == gsize * target) {
-      unsigned t = __hip_atomic_fetch_add(top_p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (t + 1 == ngroups * target)
-        __hip_atomic_store(gen_p, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ bool grid_arrive_wait(const GridBarrier &gb, unsigned target) {
+  const unsigned nwg = gridDim.x;
+  const unsigned ngroups = nwg < 8 ? nwg : 8;
+  const unsigned g = blockIdx.x % ngroups;
+  const unsigned gsize = (nwg - g + ngroups - 1) / ngroups;
+  unsigned *gen_p = gb.state;
+  unsigned old = __hip_atomic_fetch_add(gb.state + 64 + 32 * g, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (old + 1 == gsize * target) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned t = __hip_atomic_fetch_add(gb.state + 32, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t + 1 == ngroups * target) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(gen_p, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    int ab = 0;
-    const uint64_t t0 = (uint64_t)wall_clock64();
-    while (__hip_atomic_load(gen_p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
-      if ((uint64_t)wall_clock64() - t0 > gb.limit_ticks) {
-        __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ab = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    s_abort = ab;
   }
-  __syncthreads();
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  while (__hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if ((uint64_t)wall_clock64() - t0 > gb.limit_ticks) {
+      __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// Workgroup-wide form: call from every thread.  Only wave 0's writes before
+// the call are published (other waves must hand their data to wave 0, e.g.
+// through LDS, before it is written out) unless all_release is set, in which
+// case every wave first makes its own writes visible at device scope.
+__device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen, bool all_release = false) {
+  __shared__ int s_ok;
+  if (all_release) __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_ok = grid_arrive_wait(gb, gen + 1) ? 1 : 0;
+  __syncthreads();
   gen += 1;
-  return s_abort == 0;
+  return s_ok != 0;
 }
 
 // ---------------------------------------------------------------------------

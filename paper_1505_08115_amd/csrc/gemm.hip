@@ -25,8 +25,14 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBK = 16;
-constexpr int kPad = 4;
+#ifndef RQ_GEMM_BK
+#define RQ_GEMM_BK 16
+#endif
+#ifndef RQ_GEMM_PAD
+#define RQ_GEMM_PAD 4
+#endif
+constexpr int kBK = RQ_GEMM_BK;
+constexpr int kPad = RQ_GEMM_PAD;
 
 // Matrix-core instruction per element type.  Both are 16 x 16 x 4 with lane l
 // supplying X[l%16][l/16] and Y[l/16][l%16]; they differ in where D lands:

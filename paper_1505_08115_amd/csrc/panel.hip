@@ -81,9 +81,15 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         g += __shfl_xor(g, 4, 64);
         if (sub == 0 && c < ws) {
           const double h = (j >= rbeg && j < rbeg + nrow) ? X[c * rpw + (int)(j - rbeg)] : 0.0;
-          double *mp = part_cs + ((size_t)buf * nwg + wg) * 2 * W;
-          mp[c - jj] = g;
-          mp[W + (c - jj)] = h;
+          sc[c - jj] = g;
+          sc[W + (c - jj)] = h;
+        }
+        __syncthreads();
+        // wave 0 publishes the 2E partial sums of this workgroup
+        if (t < 2 * W) {
+          const int e = t;
+          if ((e < W && e < E) || (e >= W && e - W < E))
+            part_cs[((size_t)buf * nwg + wg) * 2 * W + e] = sc[e];
         }
       }
       ok = grid_sync(gb, gen);
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       }
       __syncthreads();
     }
-    ok = grid_sync(gb, gen);
+    ok = grid_sync(gb, gen, true);
     if (!ok) break;
     {
       const int E = ws * nb;
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         p.red[e] = acc;
       }
     }
-    ok = grid_sync(gb, gen);
+    ok = grid_sync(gb, gen, true);
     if (!ok) break;
     // Gram rows -> S (column j = cs + tt holds v_q^T v_j for q < cs + ws)
     if (wg == 0)
@@ -245,21 +251,67 @@ size_t panel_lds_doubles(int rpw, int nb) {
   return (size_t)W * rpw + (size_t)W * (rpw + 1) + (size_t)W * nb + W * W + 320 + W;
 }
 
-// T (nb x nb, upper triangular) from tau and the Gram matrix S.  Row i of T
-// depends only on earlier entries of the same row: T(i, j) = -tau_j *
-// sum_{q=i}^{j-1} T(i, q) S(q, j), T(i, i) = tau_i.  One thread per row.
-__global__ __launch_bounds__(64) void wy_t_kernel(int nb, const double *__restrict__ tau,
-                                                  const double *__restrict__ S, double *__restrict__ T,
-                                                  int64_t ldt) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= nb) return;
-  for (int j = 0; j < i; ++j) T[i + (int64_t)j * ldt] = 0.0;
-  T[i + (int64_t)i * ldt] = tau[i];
-  for (int j = i + 1; j < nb; ++j) {
-    double acc = 0.0;
-    const double *sj = S + (int64_t)j * nb;
-    for (int q = i; q < j; ++q) acc += T[i + (int64_t)q * ldt] * sj[q];
-    T[i + (int64_t)j * ldt] = -tau[j] * acc;
+// T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
+// matrix S = V^T V, by blocks of W columns.  With the recurrence
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) S(0:j, j) and its block
+// form T = [T_11, -T_11 S_12 T_22; 0, T_22]:
+//   1. every diagonal block T_JJ by the recurrence (all blocks in parallel,
+//      held in LDS);
+//   2. for J = 1, 2, ...: Z = S(0:c, J) T_JJ, then T(0:c, J) = -T(0:c, 0:c) Z
+//      with c = J*W, using the block columns finished before.
+// S(q, j) is read only for q < (J+1)*W, the part the panel kernel fills.
+constexpr int kTThreads = 1024;
+
+__global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *__restrict__ tau,
+                                                         const double *__restrict__ S, double *__restrict__ T,
+                                                         int64_t ldt) {
+  extern __shared__ double sh[];   // phase 1: diagonal blocks; phase 2: Z (c x W)
+  const int t = threadIdx.x;
+  const int nslab = (nb + W - 1) / W;
+  auto D = [&](int J, int r, int c) -> double & { return sh[((size_t)J * W + r) * (W + 1) + c]; };
+  double *Zs = sh;
+  // zero T (the lower part and unused entries must read as zero)
+  for (int64_t idx = t; idx < (int64_t)nb * nb; idx += kTThreads) T[idx % nb + (idx / nb) * ldt] = 0.0;
+  // 1. diagonal blocks, all slabs at once: thread (J, r) owns row r of block J
+  for (int jj = 0; jj < W; ++jj) {
+    for (int idx = t; idx < nslab * W; idx += kTThreads) {
+      const int J = idx / W, r = idx % W, cs = J * W, ws = min(W, nb - cs);
+      if (jj >= ws || r > jj) continue;
+      if (r == jj) {
+        D(J, jj, jj) = tau[cs + jj];
+      } else {
+        double acc = 0.0;
+        const double *sc = S + (int64_t)(cs + jj) * nb + cs;
+        for (int u = r; u < jj; ++u) acc += D(J, r, u) * sc[u];
+        D(J, r, jj) = -tau[cs + jj] * acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < nslab * W * W; idx += kTThreads) {
+    const int J = idx / (W * W), r = (idx / W) % W, c = idx % W, cs = J * W, ws = min(W, nb - cs);
+    if (r < ws && c < ws) T[(cs + r) + (int64_t)(cs + c) * ldt] = r <= c ? D(J, r, c) : 0.0;
+  }
+  __syncthreads();
+  // 2. off-diagonal block columns
+  for (int J = 1; J < nslab; ++J) {
+    const int c0 = J * W, ws = min(W, nb - c0);
+    // Z = S(0:c0, J) T_JJ   (c0 x ws)
+    for (int idx = t; idx < c0 * ws; idx += kTThreads) {
+      const int q = idx % c0, c = idx / c0;
+      double acc = 0.0;
+      for (int u = 0; u <= c; ++u) acc += S[q + (int64_t)(c0 + u) * nb] * T[(c0 + u) + (int64_t)(c0 + c) * ldt];
+      Zs[q + c * c0] = acc;
+    }
+    __syncthreads();
+    // T(0:c0, J) = -T(0:c0, 0:c0) Z   (T upper triangular)
+    for (int idx = t; idx < c0 * ws; idx += kTThreads) {
+      const int i = idx % c0, c = idx / c0;
+      double acc = 0.0;
+      for (int q = i; q < c0; ++q) acc += T[i + (int64_t)q * ldt] * Zs[q + c * c0];
+      T[i + (int64_t)(c0 + c) * ldt] = -acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -302,7 +354,19 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
 
 hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(wy_t_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, nb, tau, S, T, ldt);
+  if (nb > 512) return hipErrorInvalidValue;
+  const size_t nslab = (nb + W - 1) / W;
+  const size_t dbytes = nslab * W * (W + 1) * sizeof(double);     // phase 1
+  const size_t zbytes = (nslab - 1) * W * W * sizeof(double);      // phase 2, largest c0 x W
+  const size_t bytes = dbytes > zbytes ? dbytes : zbytes;
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void *)wy_t_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kLdsDoubles * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(kTThreads), bytes, s, nb, tau, S, T, ldt);
   return hipGetLastError();
 }
 

@@ -39,33 +39,39 @@ __device__ void flag_nonfinite(int32_t *info, int block_index) {
   atomicCAS(&info[1], 0, block_index + 1);
 }
 
-// Block-wide argmax over (val, pos, idx) held at red_*[0..kQThreads).
-__device__ void block_argmax(double *rv, int *rp, int *ri) {
-  const int t = threadIdx.x;
-  for (int s = kQThreads / 2; s > 0; s >>= 1) {
-    __syncthreads();
-    if (t < s && better(rv[t + s], rp[t + s], rv[t], rp[t])) {
-      rv[t] = rv[t + s];
-      rp[t] = rp[t + s];
-      ri[t] = ri[t + s];
-    }
+// Arg-max over the lanes of one wave of (val, pos, idx); ties go to the lower
+// pos.  Every lane returns the winner.
+__device__ __forceinline__ void wave_argmax(double &v, int &p, int &i) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double v2 = __shfl_xor(v, off, 64);
+    const int p2 = __shfl_xor(p, off, 64);
+    const int i2 = __shfl_xor(i, off, 64);
+    if (better(v2, p2, v, p)) { v = v2; p = p2; i = i2; }
   }
-  __syncthreads();
+}
+
+// Squared norm as a pivot key: non-finite values never win (and are flagged).
+__device__ __forceinline__ double key_of(double x, int32_t *info, int block_index, int lane) {
+  if (!(x == x) || x > 1.79e308) {
+    if (lane == 0) flag_nonfinite(info, block_index);
+    return -0.5;
+  }
+  return x;
 }
 
 __global__ __launch_bounds__(kQThreads) void qrcp_small_kernel(QrcpSmall q, int cpw, GridBarrier gb) {
   extern __shared__ double lds[];
   const int k = q.k;
   double *Yl = lds;                           // cpw * k, column-major
-  double *nrm = Yl + (size_t)cpw * k;         // cpw   squared norms of the remaining rows
-  double *v = nrm + cpw;                      // k     reflector / winning column
-  double *rv = v + k;                         // kQThreads
-  int *rp = (int *)(rv + kQThreads);          // kQThreads
-  int *ri = rp + kQThreads;                   // kQThreads
-  int *pos = ri + kQThreads;                  // cpw   current position of each column
+  double *v = Yl + (size_t)cpw * k;           // k     reflector (winning column)
+  double *wbv = v + k;                        // kQWaves best key per wave
+  int *wbp = (int *)(wbv + kQWaves);          // kQWaves best position per wave
+  int *wbi = wbp + kQWaves;                   // kQWaves best local column per wave
+  int *pos = wbi + kQWaves;                   // cpw   current position of each column
   int *act = pos + cpw;                       // cpw   1 while not yet chosen
   __shared__ double s_tau;
-  __shared__ int s_win_wg, s_win_pos, s_win_col;
+  __shared__ int s_wpos, s_wcol, s_fail;
 
   const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -81,100 +87,102 @@ __global__ __launch_bounds__(kQThreads) void qrcp_small_kernel(QrcpSmall q, int 
     act[c] = c < nloc ? 1 : 0;
   }
   __syncthreads();
-  for (int c = wave; c < nloc; c += kQWaves) {
-    const double *y = Yl + (size_t)c * k;
-    double s = 0.0;
-    for (int r = lane; r < k; r += 64) s += y[r] * y[r];
-    s = wave_sum(s);
-    if (lane == 0) nrm[c] = s;
+  // initial norms over all k rows; every wave keeps its best column
+  {
+    double bv = -1.0;
+    int bp = INT_MAX, bi = -1;
+    for (int c = wave; c < nloc; c += kQWaves) {
+      const double *y = Yl + (size_t)c * k;
+      double s2 = 0.0;
+      for (int r = lane; r < k; r += 64) s2 += y[r] * y[r];
+      s2 = key_of(wave_sum(s2), q.info, q.block_index, lane);
+      if (better(s2, c0 + c, bv, bp)) { bv = s2; bp = c0 + c; bi = c; }
+    }
+    if (lane == 0) { wbv[wave] = bv; wbp[wave] = bp; wbi[wave] = bi; }
   }
 
   unsigned gen = 0;
   bool ok = true;
-  for (int j = 0; j < q.nsteps && ok; ++j) {
+  for (int j = 0; j < q.nsteps; ++j) {
     __syncthreads();
-    // local argmax over active columns
-    double bv = -1.0;
-    int bp = INT_MAX, bi = -1;
-    for (int c = t; c < nloc; c += kQThreads) {
-      if (!act[c]) continue;
-      double x = nrm[c];
-      if (!(x == x) || x > 1.79e308) { flag_nonfinite(q.info, q.block_index); x = -0.5; }
-      if (better(x, pos[c], bv, bp)) { bv = x; bp = pos[c]; bi = c; }
-    }
-    rv[t] = bv; rp[t] = bp; ri[t] = bi;
-    block_argmax(rv, rp, ri);
     const int buf = j & 1;
-    double *myrec = q.rec + ((size_t)buf * nwg + wg) * 4;
-    double *mycand = q.cand + ((size_t)buf * nwg + wg) * k;
-    const int lbest = ri[0];
-    if (t == 0) {
-      myrec[0] = rv[0];
-      myrec[1] = (double)rp[0];
-      myrec[2] = (double)(lbest >= 0 ? c0 + lbest : -1);
+    // wave 0: this workgroup's best candidate -> record + column in global memory
+    if (wave == 0) {
+      double bv = lane < kQWaves ? wbv[lane] : -1.0;
+      int bp = lane < kQWaves ? wbp[lane] : INT_MAX;
+      int bi = lane < kQWaves ? wbi[lane] : -1;
+      wave_argmax(bv, bp, bi);
+      double *myrec = q.rec + ((size_t)buf * nwg + wg) * 4;
+      double *mycand = q.cand + ((size_t)buf * nwg + wg) * k;
+      if (bi >= 0)
+        for (int r = j + lane; r < k; r += 64) mycand[r] = Yl[(size_t)bi * k + r];
+      if (lane == 0) {
+        myrec[0] = bv;
+        myrec[1] = (double)bp;
+        myrec[2] = (double)(bi >= 0 ? c0 + bi : -1);
+      }
     }
-    if (lbest >= 0)
-      for (int r = j + t; r < k; r += kQThreads) mycand[r] = Yl[(size_t)lbest * k + r];
     ok = grid_sync(gb, gen);
     if (!ok) break;
-    // global argmax over the published records (same order in every workgroup)
-    {
+    // wave 0: global winner, its column and the reflector (Section 3.1)
+    if (wave == 0) {
       double gv = -1.0;
       int gp = INT_MAX, gi = -1;
-      for (int w2 = t; w2 < nwg; w2 += kQThreads) {
+      for (int w2 = lane; w2 < nwg; w2 += 64) {
         const double *rr = q.rec + ((size_t)buf * nwg + w2) * 4;
         const double x = rr[0];
         const int p = (int)rr[1];
         if (rr[2] >= 0.0 && better(x, p, gv, gp)) { gv = x; gp = p; gi = w2; }
       }
-      rv[t] = gv; rp[t] = gp; ri[t] = gi;
-      block_argmax(rv, rp, ri);
-      if (t == 0) {
-        s_win_wg = ri[0];
-        s_win_pos = rp[0];
-        s_win_col = ri[0] >= 0 ? (int)q.rec[((size_t)buf * nwg + ri[0]) * 4 + 2] : -1;
-      }
-      __syncthreads();
-    }
-    if (s_win_wg < 0) { ok = false; break; }   // no candidate left: cannot happen for nsteps <= ncols
-    const int wwg = s_win_wg, wpos = s_win_pos, wcol = s_win_col;
-    const double *wc = q.cand + ((size_t)buf * nwg + wwg) * k;
-    for (int r = j + t; r < k; r += kQThreads) v[r] = wc[r];
-    __syncthreads();
-    // reflector of the winning column (Section 3.1)
-    if (wave == 0) {
-      double s = 0.0;
-      for (int r = j + lane; r < k; r += 64) s += v[r] * v[r];
-      s = wave_sum(s);
-      if (lane == 0) {
-        const double alpha = v[j];
-        double tau = 0.0, scale = 1.0;
-        if (j < k - 1 && s != 0.0) {
-          const double beta = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(s);
-          tau = (beta - alpha) / beta;
-          scale = alpha - beta;
+      wave_argmax(gv, gp, gi);
+      if (gi < 0) {
+        if (lane == 0) s_fail = 1;
+      } else {
+        const double *wc = q.cand + ((size_t)buf * nwg + gi) * k;
+        double s2 = 0.0;
+        for (int r = j + lane; r < k; r += 64) {
+          const double x = wc[r];
+          v[r] = x;
+          s2 += x * x;
         }
-        s_tau = tau;
-        rv[0] = scale;
+        s2 = wave_sum(s2);
+        double tau = 0.0, scale = 1.0;
+        const double a = wc[j];
+        if (j < k - 1 && s2 != 0.0) {
+          const double beta = (a >= 0.0 ? -1.0 : 1.0) * sqrt(s2);
+          tau = (beta - a) / beta;
+          scale = a - beta;
+        }
+        if (tau != 0.0)
+          for (int r = j + 1 + lane; r < k; r += 64) v[r] = v[r] / scale;
+        if (lane == 0) {
+          v[j] = 1.0;
+          s_tau = tau;
+          s_wpos = gp;
+          s_wcol = (int)q.rec[((size_t)buf * nwg + gi) * 4 + 2];
+          s_fail = 0;
+          if (wg == 0) q.piv[j] = gp;
+        }
       }
     }
     __syncthreads();
+    if (s_fail) { ok = false; break; }   // no candidate left: cannot happen for nsteps <= ncols
     const double tau = s_tau;
-    const double scale = rv[0];
-    __syncthreads();
-    if (tau != 0.0)
-      for (int r = j + 1 + t; r < k; r += kQThreads) v[r] = v[r] / scale;
-    if (t == 0) v[j] = 1.0;
-    // bookkeeping of positions: the winner goes to j, the column at j to wpos
-    for (int c = t; c < nloc; c += kQThreads) {
-      if (c0 + c == wcol) { act[c] = 0; pos[c] = j; }
-      else if (pos[c] == j) pos[c] = wpos;
-    }
-    if (wg == 0 && t == 0) q.piv[j] = wpos;
-    __syncthreads();
-    // apply H_j to the remaining local columns, recompute their norms
+    const int wpos = s_wpos, wcol = s_wcol;
+    // every wave: bookkeeping, H_j applied to its remaining columns, new norms
+    double bv = -1.0;
+    int bp = INT_MAX, bi = -1;
     for (int c = wave; c < nloc; c += kQWaves) {
       if (!act[c]) continue;
+      if (c0 + c == wcol) {
+        if (lane == 0) { act[c] = 0; pos[c] = j; }
+        continue;
+      }
+      int pc = pos[c];
+      if (pc == j) {
+        pc = wpos;
+        if (lane == 0) pos[c] = wpos;
+      }
       double *y = Yl + (size_t)c * k;
       if (tau != 0.0) {
         double d = 0.0;
@@ -183,11 +191,12 @@ __global__ __launch_bounds__(kQThreads) void qrcp_small_kernel(QrcpSmall q, int 
         const double f = tau * d;
         for (int r = j + lane; r < k; r += 64) y[r] -= f * v[r];
       }
-      double s = 0.0;
-      for (int r = j + 1 + lane; r < k; r += 64) s += y[r] * y[r];
-      s = wave_sum(s);
-      if (lane == 0) nrm[c] = s;
+      double s2 = 0.0;
+      for (int r = j + 1 + lane; r < k; r += 64) s2 += y[r] * y[r];
+      s2 = key_of(wave_sum(s2), q.info, q.block_index, lane);
+      if (better(s2, pc, bv, bp)) { bv = s2; bp = pc; bi = c; }
     }
+    if (lane == 0) { wbv[wave] = bv; wbp[wave] = bp; wbi[wave] = bi; }
   }
   if (!ok && q.info && t == 0) atomicExch(&q.info[2], 1);
   __syncthreads();
@@ -232,7 +241,8 @@ __global__ __launch_bounds__(256) void scatter_moved_kernel(T *__restrict__ A, i
 }
 
 size_t lds_doubles(int k, int cpw) {
-  return (size_t)cpw * k + cpw + k + kQThreads + (size_t)(3 * kQThreads + 2 * cpw + 1) / 2;
+  // Yl + v + wave bests (key, pos, idx) + pos + act
+  return (size_t)cpw * k + k + kQWaves + (size_t)(2 * kQWaves + 2 * cpw + 1) / 2;
 }
 
 }  // namespace
