@@ -59,6 +59,7 @@ struct Bump {
 
 constexpr int kSlotWords = 512;   // per cooperative launch: barrier state + abort word
 constexpr int kAbortWord = 448;
+static_assert(kBarrierWords < kAbortWord && kAbortWord < kSlotWords, "barrier slot layout");
 
 struct GemmShape {
   int64_t M, N, K;

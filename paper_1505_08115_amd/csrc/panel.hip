@@ -252,66 +252,99 @@ size_t panel_lds_doubles(int rpw, int nb) {
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
-// matrix S = V^T V, by blocks of W columns.  With the recurrence
-// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) S(0:j, j) and its block
-// form T = [T_11, -T_11 S_12 T_22; 0, T_22]:
-//   1. every diagonal block T_JJ by the recurrence (all blocks in parallel,
-//      held in LDS);
-//   2. for J = 1, 2, ...: Z = S(0:c, J) T_JJ, then T(0:c, J) = -T(0:c, 0:c) Z
-//      with c = J*W, using the block columns finished before.
+// matrix S = V^T V (Section 5.1), by blocks of W columns.  Row r of a
+// diagonal block follows the column recurrence T(r, j) = -tau_j
+// sum_{r<=u<j} T(r, u) S(u, j), T(j, j) = tau_j, which only involves row r
+// itself.  The block form T = [T_11, -T_11 S_12 T_22; 0, T_22] gives, for
+// block rows, T(I, J) = -(sum_{I<=K<J} T(I, K) S(K, J)) T(J, J): block row I
+// depends only on itself and the diagonal blocks.  So one workgroup owns
+// block row I: it computes the diagonal blocks T(J, J), J >= I, one row per
+// thread in registers, parks each in the LDS slot of its own block column,
+// then fills block columns I+1, I+2, ... from left to right, and writes the
+// whole block row (zeros left of the diagonal block) to T.
 // S(q, j) is read only for q < (J+1)*W, the part the panel kernel fills.
-constexpr int kTThreads = 1024;
+constexpr int kTThreads = 256;
+constexpr int kTBlk = W * W + 2;   // staged diagonal block of S, padded against bank conflicts
 
 __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *__restrict__ tau,
                                                          const double *__restrict__ S, double *__restrict__ T,
-                                                         int64_t ldt) {
-  extern __shared__ double sh[];   // phase 1: diagonal blocks; phase 2: Z (c x W)
+                                                         int64_t ldt, int g1, int g2) {
+  extern __shared__ double sh[];
   const int t = threadIdx.x;
   const int nslab = (nb + W - 1) / W;
-  auto D = [&](int J, int r, int c) -> double & { return sh[((size_t)J * W + r) * (W + 1) + c]; };
-  double *Zs = sh;
-  // zero T (the lower part and unused entries must read as zero)
-  for (int64_t idx = t; idx < (int64_t)nb * nb; idx += kTThreads) T[idx % nb + (idx / nb) * ldt] = 0.0;
-  // 1. diagonal blocks, all slabs at once: thread (J, r) owns row r of block J
-  for (int jj = 0; jj < W; ++jj) {
-    for (int idx = t; idx < nslab * W; idx += kTThreads) {
-      const int J = idx / W, r = idx % W, cs = J * W, ws = min(W, nb - cs);
-      if (jj >= ws || r > jj) continue;
-      if (r == jj) {
-        D(J, jj, jj) = tau[cs + jj];
-      } else {
+  const int I = blockIdx.x, cI = I * W;
+  const int ldr = nslab * W + 1;              // row stride of the block row (odd: no bank conflicts)
+  double *R = sh;                             // W x ldr: block row I, column c at R[r*ldr + c - cI]
+  double *Acc = R + (size_t)W * ldr;          // W x (W+1)
+  double *St = Acc + W * (W + 1);             // staging of S
+  auto Sg = [&](int q, int j) -> double { return (q < nb && j < nb) ? S[q + (int64_t)j * nb] : 0.0; };
+
+  // 1. diagonal blocks J >= I, g1 at a time: thread (g, r) owns row r of block I + round*g1 + g
+  for (int J0 = I; J0 < nslab; J0 += g1) {
+    const int ng = min(g1, nslab - J0);
+    __syncthreads();
+    for (int idx = t; idx < ng * W * W; idx += kTThreads) {
+      const int g = idx / (W * W), u = (idx / W) % W, jj = idx % W, cJ = (J0 + g) * W;
+      St[(size_t)g * kTBlk + u * W + jj] = Sg(cJ + u, cJ + jj);
+    }
+    __syncthreads();
+    for (int task = t; task < ng * W; task += kTThreads) {
+      const int g = task / W, r = task % W, J = J0 + g, cJ = J * W;
+      const double *sj = St + (size_t)g * kTBlk;
+      double *d = R + (size_t)r * ldr + (cJ - cI);   // row r of T(J, J), built in place
+      for (int jj = 0; jj < W; ++jj) {
+        const double tj = cJ + jj < nb ? tau[cJ + jj] : 0.0;
         double acc = 0.0;
-        const double *sc = S + (int64_t)(cs + jj) * nb + cs;
-        for (int u = r; u < jj; ++u) acc += D(J, r, u) * sc[u];
-        D(J, r, jj) = -tau[cs + jj] * acc;
+        for (int u = r; u < jj; ++u) acc += d[u] * sj[u * W + jj];
+        d[jj] = jj < r ? 0.0 : (jj == r ? tj : -tj * acc);
       }
     }
-    __syncthreads();
-  }
-  for (int idx = t; idx < nslab * W * W; idx += kTThreads) {
-    const int J = idx / (W * W), r = (idx / W) % W, c = idx % W, cs = J * W, ws = min(W, nb - cs);
-    if (r < ws && c < ws) T[(cs + r) + (int64_t)(cs + c) * ldt] = r <= c ? D(J, r, c) : 0.0;
   }
   __syncthreads();
-  // 2. off-diagonal block columns
-  for (int J = 1; J < nslab; ++J) {
-    const int c0 = J * W, ws = min(W, nb - c0);
-    // Z = S(0:c0, J) T_JJ   (c0 x ws)
-    for (int idx = t; idx < c0 * ws; idx += kTThreads) {
-      const int q = idx % c0, c = idx / c0;
-      double acc = 0.0;
-      for (int u = 0; u <= c; ++u) acc += S[q + (int64_t)(c0 + u) * nb] * T[(c0 + u) + (int64_t)(c0 + c) * ldt];
-      Zs[q + c * c0] = acc;
+  // 2. block columns J > I: Acc = sum_K T(I, K) S(K, J), then T(I, J) = -Acc T(J, J)
+  const int c = t & (W - 1), rq = t >> 5;     // thread: column c, rows 4 rq .. 4 rq + 3
+  for (int J = I + 1; J < nslab; ++J) {
+    const int cJ = J * W;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int K0 = I; K0 < J; K0 += g2) {
+      const int nk = min(g2, J - K0);
+      __syncthreads();
+      for (int idx = t; idx < nk * W * W; idx += kTThreads) {
+        const int q = idx / W, cc = idx % W;      // q: row within the chunk
+        St[(size_t)q * W + cc] = Sg(K0 * W + q, cJ + cc);
+      }
+      __syncthreads();
+      const double *r0 = R + (size_t)(4 * rq) * ldr + (K0 * W - cI);
+      for (int q = 0; q < nk * W; ++q) {
+        const double sv = St[(size_t)q * W + c];
+        a0 += r0[q] * sv;
+        a1 += r0[ldr + q] * sv;
+        a2 += r0[2 * ldr + q] * sv;
+        a3 += r0[3 * ldr + q] * sv;
+      }
+    }
+    Acc[(4 * rq + 0) * (W + 1) + c] = a0;
+    Acc[(4 * rq + 1) * (W + 1) + c] = a1;
+    Acc[(4 * rq + 2) * (W + 1) + c] = a2;
+    Acc[(4 * rq + 3) * (W + 1) + c] = a3;
+    __syncthreads();
+    const double *dj = R + (cJ - cI);          // T(J, J) parked in this slot: row u at dj + u*ldr
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u <= c; ++u) {
+      const double dv = dj[(size_t)u * ldr + c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] += Acc[(4 * rq + q) * (W + 1) + u] * dv;
     }
     __syncthreads();
-    // T(0:c0, J) = -T(0:c0, 0:c0) Z   (T upper triangular)
-    for (int idx = t; idx < c0 * ws; idx += kTThreads) {
-      const int i = idx % c0, c = idx / c0;
-      double acc = 0.0;
-      for (int q = i; q < c0; ++q) acc += T[i + (int64_t)q * ldt] * Zs[q + c * c0];
-      T[i + (int64_t)(c0 + c) * ldt] = -acc;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R[(size_t)(4 * rq + q) * ldr + (cJ - cI) + c] = -o[q];
+  }
+  __syncthreads();
+  // 3. write block row I: zeros left of the diagonal block
+  const int wsI = min(W, nb - cI);
+  for (int idx = t; idx < W * nb; idx += kTThreads) {
+    const int r = idx % W, col = idx / W;
+    if (r < wsI) T[(cI + r) + (int64_t)col * ldt] = col < cI ? 0.0 : R[(size_t)r * ldr + (col - cI)];
   }
 }
 
@@ -355,10 +388,16 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
 hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt) {
   if (nb <= 0) return hipSuccess;
   if (nb > 512) return hipErrorInvalidValue;
-  const size_t nslab = (nb + W - 1) / W;
-  const size_t dbytes = nslab * W * (W + 1) * sizeof(double);     // phase 1
-  const size_t zbytes = (nslab - 1) * W * W * sizeof(double);      // phase 2, largest c0 x W
-  const size_t bytes = dbytes > zbytes ? dbytes : zbytes;
+  const int nslab = (nb + W - 1) / W;
+  const size_t fixed = (size_t)W * (nslab * W + 1) + W * (W + 1);   // must match the kernel's layout
+  if (fixed + kTBlk > kLdsDoubles) return hipErrorInvalidValue;
+  const size_t room = kLdsDoubles - fixed;
+  int g1 = (int)(room / kTBlk), g2 = (int)(room / (W * W));
+  g1 = g1 > kTThreads / W ? kTThreads / W : g1;
+  g1 = g1 > nslab ? nslab : g1;
+  g2 = g2 > nslab ? nslab : g2;
+  const size_t stage = (size_t)(g1 * kTBlk > g2 * W * W ? g1 * kTBlk : g2 * W * W);
+  const size_t bytes = (fixed + stage) * sizeof(double);
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute((const void *)wy_t_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -366,7 +405,7 @@ hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S
     if (e != hipSuccess) return e;
     attr_done = true;
   }
-  hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(kTThreads), bytes, s, nb, tau, S, T, ldt);
+  hipLaunchKernelGGL(wy_t_kernel, dim3(nslab), dim3(kTThreads), bytes, s, nb, tau, S, T, ldt, g1, g2);
   return hipGetLastError();
 }
 
