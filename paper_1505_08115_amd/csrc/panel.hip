@@ -99,8 +99,17 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         const int e = t & 63, grp = t >> 6;
         const bool valid = (e < W) ? (e < E) : (e - W < E);
         double acc = 0.0;
-        if (valid)
-          for (int w2 = grp; w2 < nwg; w2 += 4) acc += part_cs[((size_t)buf * nwg + w2) * 2 * W + e];
+        // loads issued 8 at a time, summed in workgroup order
+        for (int w0 = grp; w0 < nwg; w0 += 32) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int w2 = w0 + 4 * u;
+            x[u] = (valid && w2 < nwg) ? part_cs[((size_t)buf * nwg + w2) * 2 * W + e] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += x[u];
+        }
         sc[grp * 64 + e] = acc;
         __syncthreads();
         if (t < 64) sc[t] = ((sc[t] + sc[64 + t]) + sc[128 + t]) + sc[192 + t];
@@ -204,39 +213,49 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     }
     ok = grid_sync(gb, gen, true);
     if (!ok) break;
+    // the reduced rows V_s^T [V_0 .. V_s | A_rest] -> LDS (row tt at Wp + tt*nb)
+    for (int idx = t; idx < ws * nb; idx += kPThreads) Wp[idx] = p.red[idx];
+    __syncthreads();
     // Gram rows -> S (column j = cs + tt holds v_q^T v_j for q < cs + ws)
     if (wg == 0)
       for (int idx = t; idx < ws * (cs + ws); idx += kPThreads) {
         const int tt = idx / (cs + ws), q = idx % (cs + ws);
-        p.S[q + (int64_t)(cs + tt) * nb] = p.red[tt * nb + q];
+        p.S[q + (int64_t)(cs + tt) * nb] = Wp[tt * nb + q];
       }
-    // T_s by the forward recurrence T(0:tt, tt) = -tau_tt T(0:tt, 0:tt) V^T v_tt
-    for (int tt = 0; tt < ws; ++tt) {
-      if (t < tt) {
-        double acc = 0.0;
-        for (int u = t; u < tt; ++u) acc += Ts[t + u * W] * p.red[u * nb + cs + tt];
-        Ts[t + tt * W] = -taus[tt] * acc;
-      } else if (t == tt) {
-        Ts[tt + tt * W] = taus[tt];
-      } else if (t < W) {
-        Ts[t + tt * W] = 0.0;
+    // T_s by the recurrence T(r, tt) = -tau_tt sum_{r<=u<tt} T(r, u) v_u^T v_tt,
+    // which involves only row r: thread r builds its row without barriers
+    if (t < W) {
+      const int r = t;
+      for (int tt = 0; tt < W; ++tt) {
+        double val = 0.0;
+        if (r < ws && tt < ws) {
+          if (tt == r) {
+            val = taus[tt];
+          } else if (tt > r) {
+            double acc = 0.0;
+            for (int u = r; u < tt; ++u) acc += Ts[r + u * W] * Wp[u * nb + cs + tt];
+            val = -taus[tt] * acc;
+          }
+        }
+        Ts[r + tt * W] = val;
       }
-      __syncthreads();
     }
+    __syncthreads();
     const int rest = nb - (cs + ws);
     if (rest > 0) {
-      // Wp = T_s^T (V_s^T A_rest)
-      for (int idx = t; idx < ws * rest; idx += kPThreads) {
-        const int tt = idx / rest, c = idx % rest;
-        double acc = 0.0;
-        for (int u = 0; u <= tt; ++u) acc += Ts[u + tt * W] * p.red[u * nb + cs + ws + c];
-        Wp[tt * nb + c] = acc;
-      }
+      // Wp(:, rest) <- T_s^T (V_s^T A_rest) in place: one thread per column,
+      // rows from the last up (row tt only needs rows <= tt)
+      for (int c = cs + ws + t; c < nb; c += kPThreads)
+        for (int tt = ws - 1; tt >= 0; --tt) {
+          double acc = 0.0;
+          for (int u = 0; u <= tt; ++u) acc += Ts[u + tt * W] * Wp[u * nb + c];
+          Wp[tt * nb + c] = acc;
+        }
       __syncthreads();
       // A_rest(own rows) -= V_s Wp
       for (int idx = t; idx < nrow * rest; idx += kPThreads) {
-        const int r = idx % nrow, c = idx / nrow;
-        double *ap = p.P + (rbeg + r) + (int64_t)(cs + ws + c) * p.ldp;
+        const int r = idx % nrow, c = cs + ws + idx / nrow;
+        double *ap = p.P + (rbeg + r) + (int64_t)c * p.ldp;
         double acc = *ap;
         for (int tt = 0; tt < ws; ++tt) acc -= X[tt * rpw + r] * Wp[tt * nb + c];
         *ap = acc;
@@ -276,7 +295,9 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
   const int ldr = nslab * W + 1;              // row stride of the block row (odd: no bank conflicts)
   double *R = sh;                             // W x ldr: block row I, column c at R[r*ldr + c - cI]
   double *Acc = R + (size_t)W * ldr;          // W x (W+1)
-  double *St = Acc + W * (W + 1);             // staging of S
+  double *taul = Acc + W * (W + 1);           // nslab*W: tau, zero past nb
+  double *St = taul + nslab * W;              // staging of S
+  for (int i = t; i < nslab * W; i += kTThreads) taul[i] = i < nb ? tau[i] : 0.0;
   auto Sg = [&](int q, int j) -> double { return (q < nb && j < nb) ? S[q + (int64_t)j * nb] : 0.0; };
 
   // 1. diagonal blocks J >= I, g1 at a time: thread (g, r) owns row r of block I + round*g1 + g
@@ -293,8 +314,9 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
       const double *sj = St + (size_t)g * kTBlk;
       double *d = R + (size_t)r * ldr + (cJ - cI);   // row r of T(J, J), built in place
       for (int jj = 0; jj < W; ++jj) {
-        const double tj = cJ + jj < nb ? tau[cJ + jj] : 0.0;
+        const double tj = taul[cJ + jj];
         double acc = 0.0;
+#pragma unroll 4
         for (int u = r; u < jj; ++u) acc += d[u] * sj[u * W + jj];
         d[jj] = jj < r ? 0.0 : (jj == r ? tj : -tj * acc);
       }
@@ -315,6 +337,7 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
       }
       __syncthreads();
       const double *r0 = R + (size_t)(4 * rq) * ldr + (K0 * W - cI);
+#pragma unroll 8
       for (int q = 0; q < nk * W; ++q) {
         const double sv = St[(size_t)q * W + c];
         a0 += r0[q] * sv;
@@ -389,7 +412,7 @@ hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S
   if (nb <= 0) return hipSuccess;
   if (nb > 512) return hipErrorInvalidValue;
   const int nslab = (nb + W - 1) / W;
-  const size_t fixed = (size_t)W * (nslab * W + 1) + W * (W + 1);   // must match the kernel's layout
+  const size_t fixed = (size_t)W * (nslab * W + 1) + W * (W + 1) + (size_t)nslab * W;   // the kernel's layout
   if (fixed + kTBlk > kLdsDoubles) return hipErrorInvalidValue;
   const size_t room = kLdsDoubles - fixed;
   int g1 = (int)(room / kTBlk), g2 = (int)(room / (W * W));

@@ -17,6 +17,14 @@
 // tracked per column, so the swaps themselves never move data; at the end
 // each column's final position (dest) and the list of columns that moved are
 // written for the data-movement kernels.
+//
+// Two kernels implement this.  For a sketch (k = b + p <= 512 rows, many
+// columns) the columns live in registers: 8 lanes share a column, each
+// holding every 8th row, so applying a reflector and recomputing a norm is a
+// few register FMAs and a 3-step shuffle reduction per lane, and one
+// workgroup of 512 threads holds 64 columns (k <= 448).  For taller inputs
+// (the classical last block, k up to the LDS size) the columns live in LDS,
+// one wave per column at a time.
 #include <climits>
 
 #include "common.h"
@@ -209,6 +217,206 @@ __global__ __launch_bounds__(kQThreads) void qrcp_small_kernel(QrcpSmall q, int 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident form (k <= 8 * RPL).
+constexpr int kRLanes = 8;                         // lanes per column
+constexpr int kRCols = kQThreads / kRLanes;        // 64 columns per workgroup
+constexpr int kRMaxRows = 448;                   // 56 registers of rows per lane at most
+
+template <int RPL>
+__global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBarrier gb) {
+  constexpr int KP = kRLanes * RPL;                // padded row count
+  __shared__ double v[KP];                         // reflector, rows >= j valid
+  __shared__ double cb[kQWaves][KP];               // each wave's best column
+  __shared__ double wbv[kQWaves];
+  __shared__ int wbp[kQWaves], wbi[kQWaves];
+  __shared__ double s_tau;
+  __shared__ int s_wpos, s_wcol, s_fail;
+
+  const int k = q.k;
+  const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6, sub = lane & (kRLanes - 1);
+  const int col = wg * kRCols + (t >> 3);          // this lane group's column
+  const bool valid = col < q.ncols;
+
+  double y[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = sub + kRLanes * i;
+    y[i] = (valid && r < k) ? q.Y[r + (int64_t)col * q.ldy] : 0.0;
+  }
+  for (int r = t; r < KP; r += kQThreads) v[r] = 0.0;
+  int pos = col, act = valid ? 1 : 0;
+
+  // group sum over the 8 lanes of a column
+  auto gsum = [](double x) {
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 4, 64);
+    return x;
+  };
+  // wave arg-max over the 8 columns of a wave (lanes of a group agree)
+  auto wmax = [](double &bv, int &bp, int &bi) {
+#pragma unroll
+    for (int off = 8; off <= 32; off <<= 1) {
+      const double v2 = __shfl_xor(bv, off, 64);
+      const int p2 = __shfl_xor(bp, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      if (better(v2, p2, bv, bp)) { bv = v2; bp = p2; bi = i2; }
+    }
+  };
+  // publish this wave's best column (values of rows >= row0) to LDS
+  auto wave_best = [&](double key, int row0) {
+    double bv = act ? key : -1.0;
+    int bp = act ? pos : INT_MAX, bi = act ? col : -1;
+    wmax(bv, bp, bi);
+    if (bi >= 0 && col == bi) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = sub + kRLanes * i;
+        if (r >= row0) cb[wave][r] = y[i];
+      }
+    }
+    if (lane == 0) { wbv[wave] = bv; wbp[wave] = bp; wbi[wave] = bi; }
+  };
+
+  {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) s2 += y[i] * y[i];
+    s2 = gsum(s2);
+    s2 = key_of(s2, q.info, q.block_index, valid ? sub : 1);
+    wave_best(s2, 0);
+  }
+
+  unsigned gen = 0;
+  bool ok = true;
+  for (int j = 0; j < q.nsteps; ++j) {
+    __syncthreads();
+    const int buf = j & 1;
+    // wave 0: this workgroup's best candidate -> record + column in global memory
+    if (wave == 0) {
+      double bv = lane < kQWaves ? wbv[lane] : -1.0;
+      int bp = lane < kQWaves ? wbp[lane] : INT_MAX;
+      int bw = lane < kQWaves ? lane : -1;
+      wave_argmax(bv, bp, bw);
+      double *myrec = q.rec + ((size_t)buf * nwg + wg) * 4;
+      double *mycand = q.cand + ((size_t)buf * nwg + wg) * k;
+      const int bi = bw >= 0 ? wbi[bw] : -1;
+      if (bi >= 0)
+        for (int r = j + lane; r < k; r += 64) mycand[r] = cb[bw][r];
+      if (lane == 0) {
+        myrec[0] = bv;
+        myrec[1] = (double)bp;
+        myrec[2] = (double)bi;
+      }
+    }
+    ok = grid_sync(gb, gen);
+    if (!ok) break;
+    // wave 0: global winner, its column and the reflector (Section 3.1)
+    if (wave == 0) {
+      double gv = -1.0;
+      int gp = INT_MAX, gi = -1;
+      double rv[4], rp[4], rc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {           // nwg <= 256: all records in one round of loads
+        const int w2 = lane + 64 * u;
+        const double *rr = q.rec + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 4;
+        rv[u] = rr[0]; rp[u] = rr[1]; rc[u] = rr[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {           // gi packs (workgroup << 16) | column
+        const int w2 = lane + 64 * u;
+        if (w2 < nwg && rc[u] >= 0.0 && better(rv[u], (int)rp[u], gv, gp)) {
+          gv = rv[u]; gp = (int)rp[u]; gi = (w2 << 16) | (int)rc[u];
+        }
+      }
+      wave_argmax(gv, gp, gi);
+      const int gcol = gi & 0xFFFF;
+      gi = gi < 0 ? -1 : gi >> 16;
+      if (gi < 0) {
+        if (lane == 0) s_fail = 1;
+      } else {
+        const double *wc = q.cand + ((size_t)buf * nwg + gi) * k;
+        double xs[kRMaxRows / 64];
+#pragma unroll
+        for (int u = 0; u < kRMaxRows / 64; ++u) {
+          const int r = j + lane + 64 * u;
+          xs[u] = r < k ? wc[r] : 0.0;
+        }
+        double s2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRMaxRows / 64; ++u) s2 += xs[u] * xs[u];
+        s2 = wave_sum(s2);
+        double tau = 0.0, scale = 1.0;
+        const double a = __shfl(xs[0], 0, 64);   // row j
+        if (j < k - 1 && s2 != 0.0) {
+          const double beta = (a >= 0.0 ? -1.0 : 1.0) * sqrt(s2);
+          tau = (beta - a) / beta;
+          scale = a - beta;
+        }
+#pragma unroll
+        for (int u = 0; u < kRMaxRows / 64; ++u) {
+          const int r = j + lane + 64 * u;
+          if (r < k) v[r] = (r == j) ? 1.0 : (tau != 0.0 ? xs[u] / scale : xs[u]);
+        }
+        if (lane == 0) {
+          s_tau = tau;
+          s_wpos = gp;
+          s_wcol = gcol;
+          s_fail = 0;
+          if (wg == 0) q.piv[j] = gp;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_fail) { ok = false; break; }   // no candidate left: cannot happen for nsteps <= ncols
+    const double tau = s_tau;
+    const int wpos = s_wpos, wcol = s_wcol;
+    // every column group: bookkeeping, H_j applied, new norm over rows > j
+    if (act && col == wcol) {
+      act = 0;
+      pos = j;
+    } else if (act && pos == j) {
+      pos = wpos;
+    }
+    double s2 = 0.0;
+    if (tau != 0.0) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = sub + kRLanes * i;
+        if (r >= j) d += v[r] * y[i];
+      }
+      d = gsum(d);
+      const double f = act ? tau * d : 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = sub + kRLanes * i;
+        if (r >= j) y[i] -= f * v[r];
+        if (r > j) s2 += y[i] * y[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = sub + kRLanes * i;
+        if (r > j) s2 += y[i] * y[i];
+      }
+    }
+    s2 = gsum(s2);
+    s2 = key_of(s2, q.info, q.block_index, act ? sub : 1);
+    wave_best(s2, j + 1);
+  }
+  if (!ok && q.info && t == 0) atomicExch(&q.info[2], 1);
+  if (valid && sub == 0) {
+    q.dest[col] = pos;
+    if (pos != col) {
+      const int slot = atomicAdd(q.moved_cnt, 1);
+      if (slot < 2 * q.nsteps) q.moved[slot] = col;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gather_moved_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
                                                            int64_t r0, const int32_t *__restrict__ moved,
@@ -247,8 +455,19 @@ size_t lds_doubles(int k, int cpw) {
 
 }  // namespace
 
+static int rpl_for(int k) {
+  const int r = (k + kRLanes - 1) / kRLanes;
+  return r <= 4 ? 4 : ((r + 7) / 8) * 8;
+}
+
 int qrcp_small_config(int k, int ncols, int *cpw) {
   if (k < 1 || ncols < 1) return 0;
+  if (k <= kRMaxRows) {
+    const int nwg = (ncols + kRCols - 1) / kRCols;   // at most 16384 columns (16-bit column ids)
+    if (nwg > 256) return 0;
+    *cpw = kRCols;
+    return nwg;
+  }
   int maxc = 0;
   for (int c = 1; c <= 4096; ++c) {
     if (lds_doubles(k, c) > kLdsDoubles) break;
@@ -267,10 +486,30 @@ int qrcp_small_config(int k, int ncols, int *cpw) {
 size_t qrcp_small_rec_doubles(int nwg) { return (size_t)2 * nwg * 4; }
 size_t qrcp_small_cand_doubles(int nwg, int k) { return (size_t)2 * nwg * k; }
 
+template <int RPL>
+static hipError_t launch_reg(hipStream_t s, int nwg, const QrcpSmall &q) {
+  QrcpSmall qq = q;
+  GridBarrier gb{q.bar, q.abort_flag, q.limit_ticks};
+  void *args[] = {&qq, &gb};
+  return hipLaunchCooperativeKernel((const void *)qrcp_reg_kernel<RPL>, dim3(nwg), dim3(kQThreads), args, 0, s);
+}
+
 hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
   int cpw = 0;
   const int nwg = qrcp_small_config(q.k, q.ncols, &cpw);
   if (nwg == 0) return hipErrorInvalidValue;
+  if (q.k <= kRMaxRows) {
+    switch (rpl_for(q.k)) {
+      case 4: return launch_reg<4>(s, nwg, q);
+      case 8: return launch_reg<8>(s, nwg, q);
+      case 16: return launch_reg<16>(s, nwg, q);
+      case 24: return launch_reg<24>(s, nwg, q);
+      case 32: return launch_reg<32>(s, nwg, q);
+      case 40: return launch_reg<40>(s, nwg, q);
+      case 48: return launch_reg<48>(s, nwg, q);
+      default: return launch_reg<56>(s, nwg, q);
+    }
+  }
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute((const void *)qrcp_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

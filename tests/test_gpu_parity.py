@@ -113,6 +113,8 @@ SMALL = [
     (130, 100, 128, 3, "perm", 0, "classical"),    # b >= n: one block, the tail
     (257, 257, 16, 8, "perm", 0, "sampled"),       # sampled tail
     (400, 300, 64, 10, "perm", 100, "classical"),  # truncated rank, partial block
+    (1500, 100, 64, 8, "perm", 0, "classical"),    # tall tail: 1436 x 36 last block (LDS-resident QRCP)
+    (2000, 1100, 256, 190, "perm", 512, "classical"),  # k = 446 sketch rows, two blocks
     (96, 96, 16, 4, "ortho", 0, "classical"),
     (300, 210, 32, 6, "ortho", 0, "classical"),
     (256, 256, 64, 10, "ortho", 100, "classical"),
