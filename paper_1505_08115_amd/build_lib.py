@@ -37,7 +37,27 @@ def build(verbose=False):
     if verbose and errs.strip():
         print(errs, file=sys.stderr)
     os.replace(out_tmp, LIB)
+    build_driver(hipcc, verbose)
     return LIB
+
+
+DRIVER_SRC = os.path.join(PKG, "driver", "rqrcp_bench.hip")
+DRIVER = os.path.join(PKG, "rqrcp_bench")
+
+
+def build_driver(hipcc, verbose=False):
+    """The standalone C-ABI driver (linked against the in-tree librqrcp.so)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = [hipcc, *flags, "-I", os.path.join(ROOT, "include"), DRIVER_SRC, "-L", PKG, "-lrqrcp",
+           "-Wl,-rpath,$ORIGIN", "-o", DRIVER + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        errs = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError("hipcc failed on the driver:\n" + errs)
+    os.replace(DRIVER + ".tmp", DRIVER)
+    return DRIVER
 
 
 if __name__ == "__main__":

@@ -602,10 +602,10 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
                        (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
-          GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0};
+          GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0, true};
           CHK(launch_gemm_f64(s, gu, gpart), "C -= (V T^T) W");
         } else {
-          GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f};
+          GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
           CHK(launch_gemm<float>(s, gu, gpart32), "C -= (V T^T) W");
         }
       }

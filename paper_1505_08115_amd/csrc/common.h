@@ -103,6 +103,7 @@ struct Gemm {
   const T *B; int64_t ldb;
   T *C; int64_t ldc;
   T alpha, beta;
+  bool trailing = false;   // the factorization's trailing update (a separate kernel name in profiles)
 };
 typedef Gemm<double> GemmF64;
 typedef Gemm<float> GemmF32;

@@ -55,7 +55,9 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int drow(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT>
+// TRAIL only renames the trailing-update instance (C -= (V T^T) W) so that
+// profiles show it as a kernel of its own.
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                    const T *__restrict__ A, int64_t lda,
                                                    const T *__restrict__ B, int64_t ldb,
@@ -181,7 +183,14 @@ hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kch
   if (splits > 1)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, true>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
                        g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
-  else
+  else if constexpr (!TA && !TB) {
+    if (g.trailing)
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false, false, false, true>), grid, dim3(256), 0, s, g.M, g.N, g.K,
+                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    else
+      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
+                         g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+  } else
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
                        g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   return hipGetLastError();
