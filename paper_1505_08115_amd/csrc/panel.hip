@@ -26,6 +26,7 @@ namespace rq {
 namespace {
 
 constexpr int W = kPanelW;
+typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kPThreads = 256;
 constexpr size_t kLdsDoubles = 20480 - 256;
 
@@ -38,9 +39,10 @@ __device__ void flag_nonfinite(int32_t *info, int block_index) {
 __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw, GridBarrier gb) {
   extern __shared__ double lds[];
   const int nb = p.nb;
-  const int ldz = rpw + 1;
-  double *X = lds;                          // W x rpw   slab (own rows), column c at X + c*rpw
-  double *Zc = X + (size_t)W * rpw;         // W x ldz   staged columns
+  const int rpw4 = (rpw + 3) & ~3;           // rows padded to the MFMA K step
+  const int ldx = rpw4 + 1, ldz = rpw4 + 1;  // odd strides: the 16 lanes of a fragment hit distinct banks
+  double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
+  double *Zc = X + (size_t)W * ldx;         // W x ldz   staged columns
   double *Wp = Zc + (size_t)W * ldz;        // W x nb    T_s^T V_s^T A_rest, row t at Wp + t*nb
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
   double *sc = Ts + W * W;                  // 320       reduction scratch
@@ -61,7 +63,16 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     const int cs = s * W, ws = min(W, nb - cs);
     for (int idx = t; idx < ws * nrow; idx += kPThreads) {
       const int c = idx / nrow, r = idx % nrow;
-      X[c * rpw + r] = p.P[(rbeg + r) + (int64_t)(cs + c) * p.ldp];
+      X[c * ldx + r] = p.P[(rbeg + r) + (int64_t)(cs + c) * p.ldp];
+    }
+    // pad rows (nrow .. rpw4) and absent columns (ws .. W) read as zero in the MFMA products
+    for (int idx = t; idx < W * (rpw4 - nrow); idx += kPThreads) {
+      const int c = idx / (rpw4 - nrow), r = nrow + idx % (rpw4 - nrow);
+      X[c * ldx + r] = 0.0;
+    }
+    for (int idx = t; idx < (W - ws) * nrow; idx += kPThreads) {
+      const int c = ws + idx / nrow, r = idx % nrow;
+      X[c * ldx + r] = 0.0;
     }
     __syncthreads();
     for (int jj = 0; jj < ws && ok; ++jj, ++step) {
@@ -74,13 +85,13 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         double g = 0.0;
         if (c < ws) {
           int r0 = (int)max((int64_t)0, j - rbeg);
-          for (int r = r0 + sub; r < nrow; r += 8) g += X[jj * rpw + r] * X[c * rpw + r];
+          for (int r = r0 + sub; r < nrow; r += 8) g += X[jj * ldx + r] * X[c * ldx + r];
         }
         g += __shfl_xor(g, 1, 64);
         g += __shfl_xor(g, 2, 64);
         g += __shfl_xor(g, 4, 64);
         if (sub == 0 && c < ws) {
-          const double h = (j >= rbeg && j < rbeg + nrow) ? X[c * rpw + (int)(j - rbeg)] : 0.0;
+          const double h = (j >= rbeg && j < rbeg + nrow) ? X[c * ldx + (int)(j - rbeg)] : 0.0;
           sc[c - jj] = g;
           sc[W + (c - jj)] = h;
         }
@@ -142,12 +153,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         if (rg < j) continue;
         if (rg == j) {
           if (tau != 0.0)
-            for (int c = jj + 1; c < ws; ++c) X[c * rpw + r] -= sc[256 + c - jj];
-          X[jj * rpw + r] = beta;
+            for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[256 + c - jj];
+          X[jj * ldx + r] = beta;
         } else if (tau != 0.0) {
-          const double vr = X[jj * rpw + r] / scale;
-          X[jj * rpw + r] = vr;
-          for (int c = jj + 1; c < ws; ++c) X[c * rpw + r] -= sc[256 + c - jj] * vr;
+          const double vr = X[jj * ldx + r] / scale;
+          X[jj * ldx + r] = vr;
+          for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[256 + c - jj] * vr;
         }
       }
       __syncthreads();
@@ -158,43 +169,46 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     for (int idx = t; idx < ws * nrow; idx += kPThreads) {
       const int c = idx / nrow, r = idx % nrow;
       const int64_t rg = rbeg + r, jc = cs + c;
-      const double x = X[c * rpw + r];
+      const double x = X[c * ldx + r];
       p.P[rg + jc * p.ldp] = x;
       const double ve = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
       p.V[rg + jc * p.ldv] = ve;
-      X[c * rpw + r] = ve;
+      X[c * ldx + r] = ve;
     }
-    for (int idx = t; idx < (W - ws) * rpw; idx += kPThreads) X[ws * rpw + idx] = 0.0;
     __syncthreads();
-    // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest]
+    // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest], on the
+    // matrix cores: per 32-column chunk a 32 x 32 output, one 16 x 16 block
+    // per wave (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j] from
+    // lane j + 16k, D[i][j] in lane j + 16 (i%4), register i/4)
     double *mypart = part_up + (size_t)wg * W * nb;
+    const int lane = t & 63, wave = t >> 6, li = lane & 15, lk = lane >> 4;
     for (int cc = 0; cc < nb; cc += 32) {
-      for (int idx = t; idx < 32 * nrow; idx += kPThreads) {
-        const int c = idx / nrow, r = idx % nrow, col = cc + c;
+      for (int idx = t; idx < 32 * rpw4; idx += kPThreads) {
+        const int c = idx / rpw4, r = idx % rpw4, col = cc + c;
         double z = 0.0;
-        if (col < nb) {
+        if (col < nb && r < nrow) {
           if (col >= cs + ws) z = p.P[(rbeg + r) + (int64_t)col * p.ldp];
-          else if (col >= cs) z = X[(col - cs) * rpw + r];
+          else if (col >= cs) z = X[(col - cs) * ldx + r];
           else z = p.V[(rbeg + r) + (int64_t)col * p.ldv];
         }
         Zc[c * ldz + r] = z;
       }
       __syncthreads();
       {
-        const int c = t & 31, tg = t >> 5;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const double *x0 = X + (tg * 4 + 0) * rpw, *x1 = X + (tg * 4 + 1) * rpw;
-        const double *x2 = X + (tg * 4 + 2) * rpw, *x3 = X + (tg * 4 + 3) * rpw;
-        const double *zc = Zc + c * ldz;
-        for (int r = 0; r < nrow; ++r) {
-          const double z = zc[r];
-          a0 += x0[r] * z; a1 += x1[r] * z; a2 += x2[r] * z; a3 += x3[r] * z;
+        const int ib = wave & 1, jb = wave >> 1;
+        const double *xa = X + (16 * ib + li) * ldx + lk;
+        const double *zb = Zc + (16 * jb + li) * ldz + lk;
+        d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        int k0 = 0;
+        for (; k0 + 8 <= rpw4; k0 += 8) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0], zb[k0], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0 + 4], zb[k0 + 4], acc1, 0, 0, 0);
         }
-        if (cc + c < nb) {
-          const double av[4] = {a0, a1, a2, a3};
+        if (k0 < rpw4) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0], zb[k0], acc0, 0, 0, 0);
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (tg * 4 + q < ws) mypart[(tg * 4 + q) * nb + cc + c] = av[q];
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * ib + 4 * q + lk, col = cc + 16 * jb + li;
+          if (i < ws && col < nb) mypart[i * nb + col] = acc0[q] + acc1[q];
         }
       }
       __syncthreads();
@@ -252,13 +266,31 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           Wp[tt * nb + c] = acc;
         }
       __syncthreads();
-      // A_rest(own rows) -= V_s Wp
-      for (int idx = t; idx < nrow * rest; idx += kPThreads) {
-        const int r = idx % nrow, c = cs + ws + idx / nrow;
-        double *ap = p.P + (rbeg + r) + (int64_t)c * p.ldp;
-        double acc = *ap;
-        for (int tt = 0; tt < ws; ++tt) acc -= X[tt * rpw + r] * Wp[tt * nb + c];
-        *ap = acc;
+      // A_rest(own rows) -= V_s Wp on the matrix cores, computed transposed
+      // (D[i][j] = sum_tt Wp(tt, c0 + i) V_s(r0 + j, tt)) so that each lane
+      // holds consecutive rows of one column of P: 16 x 16 blocks dealt to waves
+      {
+        const int rb = (nrow + 15) / 16, cb = (rest + 15) / 16;
+        for (int blk = wave; blk < rb * cb; blk += kPThreads / 64) {
+          const int r0 = 16 * (blk % rb), c0 = 16 * (blk / rb);
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          const int ca = cs + ws + min(c0 + li, rest - 1);
+          for (int k0 = 0; k0 < ws; k0 += 4) {
+            const int tt = k0 + lk;
+            const double a = tt < ws ? Wp[tt * nb + ca] : 0.0;
+            const double bv = X[tt * ldx + min(r0 + li, rpw4 - 1)];   // zero for tt >= ws and pad rows
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+          }
+          const int r = r0 + li;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = c0 + 4 * q + lk;
+            if (r < nrow && c < rest) {
+              double *ap = p.P + (rbeg + r) + (int64_t)(cs + ws + c) * p.ldp;
+              *ap -= acc[q];
+            }
+          }
+        }
       }
     }
     __syncthreads();
@@ -267,7 +299,8 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 }
 
 size_t panel_lds_doubles(int rpw, int nb) {
-  return (size_t)W * rpw + (size_t)W * (rpw + 1) + (size_t)W * nb + W * W + 320 + W;
+  const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded strides
+  return (size_t)W * ld + (size_t)W * ld + (size_t)W * nb + W * W + 320 + W;
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram

@@ -265,17 +265,14 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
       if (better(v2, p2, bv, bp)) { bv = v2; bp = p2; bi = i2; }
     }
   };
-  // publish this wave's best column (values of rows >= row0) to LDS
-  auto wave_best = [&](double key, int row0) {
+  // publish this wave's best column to LDS (all rows; readers use rows >= j)
+  auto wave_best = [&](double key) {
     double bv = act ? key : -1.0;
     int bp = act ? pos : INT_MAX, bi = act ? col : -1;
     wmax(bv, bp, bi);
     if (bi >= 0 && col == bi) {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub + kRLanes * i;
-        if (r >= row0) cb[wave][r] = y[i];
-      }
+      for (int i = 0; i < RPL; ++i) cb[wave][sub + kRLanes * i] = y[i];
     }
     if (lane == 0) { wbv[wave] = bv; wbp[wave] = bp; wbi[wave] = bi; }
   };
@@ -286,7 +283,7 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
     for (int i = 0; i < RPL; ++i) s2 += y[i] * y[i];
     s2 = gsum(s2);
     s2 = key_of(s2, q.info, q.block_index, valid ? sub : 1);
-    wave_best(s2, 0);
+    wave_best(s2);
   }
 
   unsigned gen = 0;
@@ -360,6 +357,8 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
           const int r = j + lane + 64 * u;
           if (r < k) v[r] = (r == j) ? 1.0 : (tau != 0.0 ? xs[u] / scale : xs[u]);
         }
+        // rows < j of v stay zero, so the column updates need no row masks
+        if (lane == 0 && j > 0) v[j - 1] = 0.0;
         if (lane == 0) {
           s_tau = tau;
           s_wpos = gp;
@@ -380,32 +379,34 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
     } else if (act && pos == j) {
       pos = wpos;
     }
-    double s2 = 0.0;
+    // straight-line code (no per-row branches): v is zero on rows < j and
+    // past k, the norm takes rows > j by a select
     if (tau != 0.0) {
-      double d = 0.0;
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub + kRLanes * i;
-        if (r >= j) d += v[r] * y[i];
+      for (int i = 0; i < RPL; i += 2) {
+        d0 += v[sub + kRLanes * i] * y[i];
+        if (i + 1 < RPL) d1 += v[sub + kRLanes * (i + 1)] * y[i + 1];
       }
-      d = gsum(d);
+      const double d = gsum(d0 + d1);
       const double f = act ? tau * d : 0.0;
+      __asm__ volatile("" ::: "memory");   // re-read v below rather than hold it in registers
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub + kRLanes * i;
-        if (r >= j) y[i] -= f * v[r];
-        if (r > j) s2 += y[i] * y[i];
-      }
-    } else {
+      for (int i = 0; i < RPL; ++i) y[i] -= f * v[sub + kRLanes * i];
+    }
+    double s20 = 0.0, s21 = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = sub + kRLanes * i;
-        if (r > j) s2 += y[i] * y[i];
+    for (int i = 0; i < RPL; i += 2) {
+      const double a = (sub + kRLanes * i > j) ? y[i] : 0.0;
+      s20 += a * a;
+      if (i + 1 < RPL) {
+        const double c = (sub + kRLanes * (i + 1) > j) ? y[i + 1] : 0.0;
+        s21 += c * c;
       }
     }
-    s2 = gsum(s2);
+    double s2 = gsum(s20 + s21);
     s2 = key_of(s2, q.info, q.block_index, act ? sub : 1);
-    wave_best(s2, j + 1);
+    wave_best(s2);
   }
   if (!ok && q.info && t == 0) atomicExch(&q.info[2], 1);
   if (valid && sub == 0) {
