@@ -9,8 +9,8 @@
 //    X = op(B)^T and Y = op(A)^T, so that D = C^T and each lane holds 16
 //    consecutive rows of a column of C: stores are contiguous segments.
 //  * 256 threads = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
-//    block of 16 x 16 MFMA tiles; K advances by BK = 16 through one LDS
-//    stage, the next K slab is prefetched into registers during the MFMAs.
+//    block of 16 x 16 MFMA tiles; K advances by BK = 16 through two LDS
+//    stages, the next K slab is prefetched into registers during the MFMAs.
 //  * Global loads are flattened so that consecutive lanes read consecutive
 //    addresses along the contiguous dimension of each operand.
 //  * Split-K: when the M x N tile grid is too small to fill 256 CUs, K is cut
@@ -57,58 +57,68 @@ template <> struct Mfma<float> {
 
 // TRAIL only renames the trailing-update instance (C -= (V T^T) W) so that
 // profiles show it as a kernel of its own.
+//
+// Each thread prefetches AE elements of the A slab and BE of the B slab; the
+// elements of one thread sit at a fixed base plus a uniform stride (the
+// flattened index t + 256 q maps to (t mod L) and (t / L) + q 256/L along the
+// contiguous dimension L), so no per-element addresses stay live.  Interior
+// tiles on full K slabs load without bounds checks.  Two LDS stages: the
+// next slab is written to the other stage while this one feeds the MFMAs,
+// one barrier per K slab.
 template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
-__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
-                                                   const T *__restrict__ A, int64_t lda,
-                                                   const T *__restrict__ B, int64_t ldb,
-                                                   T *__restrict__ C, int64_t ldc, T alpha,
-                                                   T beta, T *__restrict__ partial) {
+__global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                      const T *__restrict__ A, int64_t lda,
+                                                      const T *__restrict__ B, int64_t ldb,
+                                                      T *__restrict__ C, int64_t ldc, T alpha,
+                                                      T beta, T *__restrict__ partial) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int AE = BM * kBK / 256, BE = BN * kBK / 256;
-  __shared__ T As[kBK][BM + kPad];
-  __shared__ T Bs[kBK][BN + kPad];
+  // per-thread element coordinates: (first index, step per q) along rows/cols and k
+  constexpr int A_QI = TA ? 256 / kBK : 0, A_QK = TA ? 0 : 256 / BM;
+  constexpr int B_QJ = TB ? 0 : 256 / kBK, B_QK = TB ? 256 / BN : 0;
+  __shared__ T As[2][kBK][BM + kPad];
+  __shared__ T Bs[2][kBK][BN + kPad];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
+  const bool interior = m0 + BM <= M && n0 + BN <= N;
+
+  const int a_i = TA ? t / kBK : t % BM, a_k = TA ? t % kBK : t / BM;
+  const int b_j = TB ? t % BN : t / kBK, b_k = TB ? t / BN : t % kBK;
+  const int64_t a_step = TA ? (int64_t)A_QI * lda : (int64_t)A_QK * lda;   // pointer step per q
+  const int64_t b_step = TB ? (int64_t)B_QK * ldb : (int64_t)B_QJ * ldb;
 
   T ra[AE], rb[BE];
   auto load = [&](int64_t k0) {
+    const T *pa = TA ? A + (k0 + a_k) + (m0 + a_i) * lda : A + (m0 + a_i) + (k0 + a_k) * lda;
+    const T *pb = TB ? B + (n0 + b_j) + (k0 + b_k) * ldb : B + (k0 + b_k) + (n0 + b_j) * ldb;
+    if (interior && k0 + kBK <= kend) {
 #pragma unroll
-    for (int q = 0; q < AE; ++q) {
-      const int f = t + 256 * q;
-      const int i = TA ? f / kBK : f % BM;
-      const int kk = TA ? f % kBK : f / BM;
-      const int64_t gi = m0 + i, gk = k0 + kk;
-      ra[q] = (gi < M && gk < kend) ? (TA ? A[gk + gi * lda] : A[gi + gk * lda]) : T(0);
-    }
+      for (int q = 0; q < AE; ++q) ra[q] = pa[q * a_step];
 #pragma unroll
-    for (int q = 0; q < BE; ++q) {
-      const int f = t + 256 * q;
-      const int j = TB ? f % BN : f / kBK;
-      const int kk = TB ? f / BN : f % kBK;
-      const int64_t gj = n0 + j, gk = k0 + kk;
-      rb[q] = (gj < N && gk < kend) ? (TB ? B[gj + gk * ldb] : B[gk + gj * ldb]) : T(0);
+      for (int q = 0; q < BE; ++q) rb[q] = pb[q * b_step];
+    } else {
+#pragma unroll
+      for (int q = 0; q < AE; ++q) {
+        const int64_t gi = m0 + a_i + q * A_QI, gk = k0 + a_k + q * A_QK;
+        ra[q] = (gi < M && gk < kend) ? pa[q * a_step] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < BE; ++q) {
+        const int64_t gj = n0 + b_j + q * B_QJ, gk = k0 + b_k + q * B_QK;
+        rb[q] = (gj < N && gk < kend) ? pb[q * b_step] : T(0);
+      }
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int st) {
 #pragma unroll
-    for (int q = 0; q < AE; ++q) {
-      const int f = t + 256 * q;
-      const int i = TA ? f / kBK : f % BM;
-      const int kk = TA ? f % kBK : f / BM;
-      As[kk][i] = ra[q];
-    }
+    for (int q = 0; q < AE; ++q) As[st][a_k + q * A_QK][a_i + q * A_QI] = ra[q];
 #pragma unroll
-    for (int q = 0; q < BE; ++q) {
-      const int f = t + 256 * q;
-      const int j = TB ? f % BN : f / kBK;
-      const int kk = TB ? f / BN : f % kBK;
-      Bs[kk][j] = rb[q];
-    }
+    for (int q = 0; q < BE; ++q) Bs[st][b_k + q * B_QK][b_j + q * B_QJ] = rb[q];
   };
 
   acc_t acc[TM][TN];
@@ -118,25 +128,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
     for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{T(0), T(0), T(0), T(0)};
 
   const int lr = lane & 15, lk = lane >> 4;
-  if (kbeg < kend) load(kbeg);
+  int st = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    stash(0);
+  }
+  __syncthreads();
   for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + kBK < kend) load(k0 + kBK);
+    const bool more = k0 + kBK < kend;
+    if (more) load(k0 + kBK);
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
       T xa[TN], yb[TM];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) xa[b] = Bs[kk + lk][wn * (BN / 2) + b * 16 + lr];
+      for (int b = 0; b < TN; ++b) xa[b] = Bs[st][kk + lk][wn * (BN / 2) + b * 16 + lr];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) yb[a] = As[kk + lk][wm * (BM / 2) + a * 16 + lr];
+      for (int a = 0; a < TM; ++a) yb[a] = As[st][kk + lk][wm * (BM / 2) + a * 16 + lr];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
           acc[a][b] = Mfma<T>::mma(xa[b], yb[a], acc[a][b]);
     }
+    if (more) stash(st ^ 1);
+    __syncthreads();
+    st ^= 1;
   }
 
 #pragma unroll
