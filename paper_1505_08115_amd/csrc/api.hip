@@ -65,11 +65,16 @@ struct GemmShape {
   int64_t M, N, K;
 };
 
+// Partial-product room for a GEMM of this shape, whichever engine (tiled or
+// all-rows) and transposition the call uses.
 size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
-  GemmF64 g{};
-  g.M = M; g.N = N; g.K = K;
-  const int sp = gemm_f64_splits(g);
+  int sp = 1;
+  for (int tb = 0; tb < 2; ++tb) {
+    GemmF64 g{};
+    g.M = M; g.N = N; g.K = K; g.tb = tb != 0;
+    sp = std::max(sp, gemm_f64_splits(g));
+  }
   return sp > 1 ? (size_t)sp * M * N : 0;
 }
 
@@ -77,10 +82,10 @@ struct FactorPlan {
   int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
   bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
   // FP32-storage buffers
-  size_t Pw = 0, V32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
+  size_t Pw = 0, V32 = 0, VT32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
   int nslots = 0;
   // byte offsets into the workspace
-  size_t G = 0, Y = 0, YT = 0, Vb = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
+  size_t G = 0, Y = 0, YT = 0, Vb = 0, VT = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
          piv = 0, dest = 0, moved = 0, mcnt = 0, tmp = 0, jtmp = 0, bars = 0, Acopy = 0, total = 0;
   size_t Y_doubles = 0;
 };
@@ -181,6 +186,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Y = w.take(Yd * d);
   P.YT = w.take(P.ortho ? (size_t)n * P.b * d : 0);
   P.Vb = w.take((size_t)m * P.b * d);
+  P.VT = w.take((size_t)m * P.b * d);
   P.Vt = w.take((size_t)m * P.b * d);
   P.Wb = w.take((size_t)P.b * n * d);
   P.gpart = w.take(gpart * d);
@@ -201,6 +207,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
+    P.VT32 = w.take((size_t)m * P.b * 4);
     P.Vt32 = w.take((size_t)m * P.b * 4);
     P.W32 = w.take((size_t)P.b * n * 4);
     P.gpart32 = w.take(gpart32 * 4);
@@ -407,7 +414,8 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   hipStream_t s = h->stream;
   const int64_t m = P.m, n = P.n, b = P.b, ks = P.ks;
   double *G = at<double>(work, P.G), *Y = at<double>(work, P.Y), *YT = at<double>(work, P.YT);
-  double *Vb = at<double>(work, P.Vb), *Vt = at<double>(work, P.Vt), *Wb = at<double>(work, P.Wb);
+  double *Vb = at<double>(work, P.Vb), *VT = at<double>(work, P.VT), *Vt = at<double>(work, P.Vt);
+  double *Wb = at<double>(work, P.Wb);
   double *gpart = at<double>(work, P.gpart), *Sg = at<double>(work, P.Sg);
   double *ppart = at<double>(work, P.ppart), *pred = at<double>(work, P.pred);
   double *qrec = at<double>(work, P.qrec), *qcand = at<double>(work, P.qcand);
@@ -418,7 +426,8 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   unsigned *bars = at<unsigned>(work, P.bars);
   // FP32-storage buffers
   double *Pw = at<double>(work, P.Pw);
-  float *V32 = at<float>(work, P.V32), *Vt32 = at<float>(work, P.Vt32), *W32 = at<float>(work, P.W32);
+  float *V32 = at<float>(work, P.V32), *VT32 = at<float>(work, P.VT32), *Vt32 = at<float>(work, P.Vt32);
+  float *W32 = at<float>(work, P.W32);
   float *gpart32 = at<float>(work, P.gpart32), *spart = at<float>(work, P.spart);
   float *G32 = at<float>(work, P.G32), *Y32 = at<float>(work, P.Y32);
   float *VS32 = at<float>(work, P.VS32), *TS32 = at<float>(work, P.TS32);
@@ -564,6 +573,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       }
       pq.mi = mi; pq.nb = (int)bi;
       pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+      pq.VT = VT; pq.ldvt = b;
       pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
       next_slot(&pq.bar, &pq.abort_flag);
       CHK(launch_panel_qr(s, pq), "panel QR");
@@ -584,17 +594,17 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
         if constexpr (F32) {
           CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
-          CHK(launch_copy_f64_f32(s, Vb, mi, V32, mi, mi, bi), "V to FP32");
+          CHK(launch_copy_f64_f32(s, VT, b, VT32, b, bi, mi), "V^T to FP32");
         }
       }
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
-          GemmF64 gw{true, false, bi, ni - bi, mi, Vb, mi, C, lda, Wb, bi, 1.0, 0.0};
+          GemmF64 gw{false, false, bi, ni - bi, mi, VT, b, C, lda, Wb, bi, 1.0, 0.0};
           CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
         } else {
-          GemmF32 gw{true, false, bi, ni - bi, mi, V32, mi, C, lda, W32, bi, 1.f, 0.f};
+          GemmF32 gw{false, false, bi, ni - bi, mi, VT32, b, C, lda, W32, bi, 1.f, 0.f};
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
       }

@@ -151,6 +151,7 @@ struct PanelQR {
   double *P; int64_t ldp; int64_t mi; int nb;
   double *tau;            // [nb]
   double *V; int64_t ldv; // explicit unit-lower V (mi x nb)
+  double *VT; int64_t ldvt;   // NULL, or V^T (nb x mi) written as well
   double *S;              // nb x nb Gram V^T V (column j valid for rows <= j)
   double *part;           // partial sums, panel_part_doubles()
   double *red;            // reduced sums, nb * kPanelW doubles

@@ -177,6 +177,109 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
   }
 }
 
+// Short, wide products C (M x N) = alpha op(A) B + beta C with M <= 448 (the
+// sketch Y = G X and W = V^T C): one workgroup holds all M rows of a
+// 128-column slab of C, so the large operand B is read from HBM exactly once
+// (a tiled kernel with 128-row tiles re-reads it once per row tile).  512
+// threads = 8 waves, wave w owns columns 16w .. 16w+15 of the slab and all
+// MT row blocks of 16; K is split over workgroups to fill the chip.
+constexpr int kRowsBN = 128;
+constexpr int kRowsThreads = 512;
+
+template <typename T, int MT, bool TA, bool SPLIT>
+__global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                                 const T *__restrict__ A, int64_t lda,
+                                                                 const T *__restrict__ B, int64_t ldb,
+                                                                 T *__restrict__ C, int64_t ldc, T alpha, T beta,
+                                                                 T *__restrict__ partial) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int MP = 16 * MT;                                   // padded rows
+  constexpr int AE = (MP * kBK + kRowsThreads - 1) / kRowsThreads;
+  constexpr int BE = kRowsBN * kBK / kRowsThreads;              // 4
+  __shared__ T As[2][kBK][MP + kPad];
+  __shared__ T Bs[2][kBK][kRowsBN + kPad];
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t n0 = (int64_t)blockIdx.x * kRowsBN;
+  const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+  const int64_t kend = min(K, kbeg + kchunk);
+  const bool interior = n0 + kRowsBN <= N;
+
+  // B slab (k fastest): k = t % 16, column j = t / 16 + 32 q
+  const int b_k = t % kBK, b_j = t / kBK;
+  T ra[AE], rb[BE];
+  auto load = [&](int64_t k0) {
+    const bool fullk = k0 + kBK <= kend;
+    const T *pb = B + (k0 + b_k) + (n0 + b_j) * ldb;
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const bool okq = (interior && fullk) || (n0 + b_j + 32 * q < N && k0 + b_k < kend);
+      rb[q] = okq ? pb[(int64_t)32 * q * ldb] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int f = t + kRowsThreads * q;
+      // TA: k fastest (A stored K x M); otherwise rows fastest (A stored M x K)
+      const int r = TA ? f / kBK : f % MP, kk = TA ? f % kBK : f / MP;
+      const int64_t gk = k0 + kk;
+      const bool okq = f < MP * kBK && r < M && gk < kend;
+      ra[q] = okq ? (TA ? A[gk + (int64_t)r * lda] : A[r + gk * lda]) : T(0);
+    }
+  };
+  auto stash = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < BE; ++q) Bs[st][b_k][b_j + 32 * q] = rb[q];
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int f = t + kRowsThreads * q;
+      const int r = TA ? f / kBK : f % MP, kk = TA ? f % kBK : f / MP;
+      if (f < MP * kBK) As[st][kk][r] = ra[q];
+    }
+  };
+
+  acc_t acc[MT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a) acc[a] = acc_t{T(0), T(0), T(0), T(0)};
+  const int lr = lane & 15, lk = lane >> 4;
+  int st = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+    const bool more = k0 + kBK < kend;
+    if (more) load(k0 + kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      const T xb = Bs[st][kk + lk][16 * wave + lr];
+#pragma unroll
+      for (int a = 0; a < MT; ++a) acc[a] = Mfma<T>::mma(xb, As[st][kk + lk][16 * a + lr], acc[a]);
+    }
+    if (more) stash(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+  // D = C^T: lane holds row 16 a + lr of columns 16 wave + drow(lane, r)
+#pragma unroll
+  for (int a = 0; a < MT; ++a) {
+    const int64_t row = 16 * a + lr;
+    if (row >= M) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t col = n0 + 16 * wave + Mfma<T>::drow(lane, r);
+      if (col >= N) continue;
+      const T v = acc[a][r];
+      if (SPLIT) {
+        partial[(int64_t)blockIdx.y * M * N + row + col * M] = v;
+      } else {
+        T *cp = C + row + col * ldc;
+        *cp = (beta == T(0)) ? alpha * v : alpha * v + beta * (*cp);
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t N, int splits,
                                                               const T *__restrict__ partial,
@@ -242,12 +345,72 @@ void split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   *kchunk = kc;
 }
 
+// The all-rows kernel takes products with 64 < M <= 448 (288 in FP64), A and
+// B untransposed and a long K (the sketch G X, and V^T C with V^T stored
+// explicitly); everything else goes to the tiled kernel.  (A transposed
+// operand would be read as many short strided segments, which measured
+// slower than the tiled kernel.)
+template <typename T>
+constexpr int rows_max_mt() { return sizeof(T) == 8 ? 18 : 28; }   // FP64 accumulators: 8 VGPRs per block
+
+template <typename T>
+bool use_rows(const Gemm<T> &g) {
+  return !g.ta && !g.tb && g.M > 64 && g.M <= 16 * rows_max_mt<T>() && g.K >= 1024 && g.N >= 256;
+}
+
+// One workgroup per CU (its LDS stages take most of the CU's 160 KiB), so the
+// grid should fit one round on the 256 CUs of an MI355X: a second, partial
+// round would cost nearly as much as the first.
+constexpr int64_t kRowsSlots = 256;
+
+template <typename T>
+void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
+  const int64_t tiles = (g.N + kRowsBN - 1) / kRowsBN;
+  int64_t sp = kRowsSlots / tiles;                           // tiles * splits <= one round
+  const int64_t maxsp = g.K / (kBK * 16);                    // at least 256 of K per split
+  if (sp > maxsp) sp = maxsp;
+  if (sp > 64) sp = 64;
+  if (sp < 1) sp = 1;
+  int64_t kc = (g.K + sp - 1) / sp;
+  kc = ((kc + kBK - 1) / kBK) * kBK;
+  if (kc < kBK) kc = kBK;
+  sp = (g.K + kc - 1) / kc;
+  *splits = (int)(sp < 1 ? 1 : sp);
+  *kchunk = kc;
+}
+
+template <typename T, int MT, bool TA>
+hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+  dim3 grid((unsigned)((g.N + kRowsBN - 1) / kRowsBN), (unsigned)splits);
+  if (splits > 1)
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, true>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K, kchunk,
+                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+  else
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, false>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K, kchunk,
+                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+  return hipGetLastError();
+}
+
+template <typename T, bool TA>
+hipError_t launch_rows(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+  const int mt = (int)((g.M + 15) / 16);
+  if (mt <= 8) return launch_rows_mt<T, 8, TA>(s, g, splits, kchunk, partial);
+  if (mt <= 12) return launch_rows_mt<T, 12, TA>(s, g, splits, kchunk, partial);
+  if (mt <= 18 || rows_max_mt<T>() <= 18) return launch_rows_mt<T, 18, TA>(s, g, splits, kchunk, partial);
+  if constexpr (rows_max_mt<T>() > 18) {
+    if (mt <= 24) return launch_rows_mt<T, 24, TA>(s, g, splits, kchunk, partial);
+    return launch_rows_mt<T, 28, TA>(s, g, splits, kchunk, partial);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 template <typename T>
 int gemm_splits(const Gemm<T> &g) {
   int sp; int64_t kc;
-  split_plan(g, &sp, &kc);
+  if (use_rows(g)) rows_split_plan(g, &sp, &kc);
+  else split_plan(g, &sp, &kc);
   return sp;
 }
 
@@ -255,10 +418,13 @@ template <typename T>
 hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   int splits; int64_t kchunk;
-  split_plan(g, &splits, &kchunk);
+  const bool rows = use_rows(g);
+  if (rows) rows_split_plan(g, &splits, &kchunk);
+  else split_plan(g, &splits, &kchunk);
   if (g.K <= 0) splits = 1;
   hipError_t e;
-  if (!g.ta && !g.tb) e = launch_shape<T, false, false>(s, g, splits, kchunk, partial);
+  if (rows) e = launch_rows<T, false>(s, g, splits, kchunk, partial);
+  else if (!g.ta && !g.tb) e = launch_shape<T, false, false>(s, g, splits, kchunk, partial);
   else if (g.ta && !g.tb) e = launch_shape<T, true, false>(s, g, splits, kchunk, partial);
   else if (!g.ta && g.tb) e = launch_shape<T, false, true>(s, g, splits, kchunk, partial);
   else e = launch_shape<T, true, true>(s, g, splits, kchunk, partial);

@@ -173,7 +173,23 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       p.P[rg + jc * p.ldp] = x;
       const double ve = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
       p.V[rg + jc * p.ldv] = ve;
-      X[c * ldx + r] = ve;
+    }
+    // V^T rows (slab columns fastest: 32 contiguous values per row), then X <- explicit V_s
+    if (p.VT) {
+      __syncthreads();
+      for (int idx = t; idx < ws * nrow; idx += kPThreads) {
+        const int c = idx % ws, r = idx / ws;
+        const int64_t rg = rbeg + r, jc = cs + c;
+        const double x = X[c * ldx + r];
+        p.VT[jc + rg * p.ldvt] = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
+      }
+    }
+    __syncthreads();
+    for (int idx = t; idx < ws * nrow; idx += kPThreads) {
+      const int c = idx / nrow, r = idx % nrow;
+      const int64_t rg = rbeg + r, jc = cs + c;
+      const double x = X[c * ldx + r];
+      X[c * ldx + r] = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
     }
     __syncthreads();
     // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest], on the
