@@ -232,13 +232,36 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     ok = grid_sync(gb, gen, true);
     if (!ok) break;
     {
+      // reduce-scatter: this workgroup sums elements [beg, end) over all
+      // workgroups' partials; G threads share an element, thread g taking a
+      // contiguous range of workgroups with its loads issued 8 at a time, and
+      // the G range sums are added in range order (a fixed order)
       const int E = ws * nb;
       const int per = (E + nwg - 1) / nwg;
       const int beg = wg * per, end = min(E, beg + per);
-      for (int e = beg + t; e < end; e += kPThreads) {
+      const int G = per >= kPThreads ? 1 : (per >= kPThreads / 2 ? 2 : (per >= kPThreads / 4 ? 4 : 8));
+      const int wper = (nwg + G - 1) / G;
+      const int g = t % G;
+      const int w0 = g * wper, w1 = min(nwg, w0 + wper);
+      for (int e0 = beg; e0 < end; e0 += kPThreads / G) {
+        const int e = e0 + t / G;
         double acc = 0.0;
-        for (int w2 = 0; w2 < nwg; ++w2) acc += part_up[(size_t)w2 * W * nb + e];
-        p.red[e] = acc;
+        if (e < end)
+          for (int wb = w0; wb < w1; wb += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = wb + u < w1 ? part_up[(size_t)(wb + u) * W * nb + e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += x[u];
+          }
+        sc[t] = acc;
+        __syncthreads();
+        if (g == 0 && e < end) {
+          double tot = sc[t];
+          for (int h = 1; h < G; ++h) tot += sc[t + h];
+          p.red[e] = tot;
+        }
+        __syncthreads();
       }
     }
     ok = grid_sync(gb, gen, true);
