@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   const int ldx = rpw4 + 1, ldz = rpw4 + 1;  // odd strides: the 16 lanes of a fragment hit distinct banks
   double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
   double *Zc = X + (size_t)W * ldx;         // W x ldz   staged columns
-  double *Wp = Zc + (size_t)W * ldz;        // W x nb    T_s^T V_s^T A_rest, row t at Wp + t*nb
+  double *Wp = Zc + (size_t)W * ldz;        // W x nb    reduced V_s^T [V_0..V_s | A_rest], row t at Wp + t*nb
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
   double *sc = Ts + W * W;                  // 320       reduction scratch
   double *taus = sc + 320;                  // W
@@ -199,15 +199,26 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     double *mypart = part_up + (size_t)wg * W * nb;
     const int lane = t & 63, wave = t >> 6, li = lane & 15, lk = lane >> 4;
     for (int cc = 0; cc < nb; cc += 32) {
-      for (int idx = t; idx < 32 * rpw4; idx += kPThreads) {
-        const int c = idx / rpw4, r = idx % rpw4, col = cc + c;
-        double z = 0.0;
-        if (col < nb && r < nrow) {
-          if (col >= cs + ws) z = p.P[(rbeg + r) + (int64_t)col * p.ldp];
-          else if (col >= cs) z = X[(col - cs) * ldx + r];
-          else z = p.V[(rbeg + r) + (int64_t)col * p.ldv];
+      // stage Z(:, cc .. cc+31); global loads issued 8 at a time (one
+      // workgroup per CU: a load per iteration would expose every round trip)
+      for (int base = 0; base < 32 * rpw4; base += 8 * kPThreads) {
+        double z[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + t + u * kPThreads;
+          const int c = idx / rpw4, r = idx % rpw4, col = cc + c;
+          z[u] = 0.0;
+          if (idx < 32 * rpw4 && col < nb && r < nrow) {
+            if (col >= cs + ws) z[u] = p.P[(rbeg + r) + (int64_t)col * p.ldp];
+            else if (col >= cs) z[u] = X[(col - cs) * ldx + r];
+            else z[u] = p.V[(rbeg + r) + (int64_t)col * p.ldv];
+          }
         }
-        Zc[c * ldz + r] = z;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + t + u * kPThreads;
+          if (idx < 32 * rpw4) Zc[(idx / rpw4) * ldz + idx % rpw4] = z[u];
+        }
       }
       __syncthreads();
       {
@@ -266,8 +277,21 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     }
     ok = grid_sync(gb, gen, true);
     if (!ok) break;
-    // the reduced rows V_s^T [V_0 .. V_s | A_rest] -> LDS (row tt at Wp + tt*nb)
-    for (int idx = t; idx < ws * nb; idx += kPThreads) Wp[idx] = p.red[idx];
+    // the reduced rows V_s^T [V_0 .. V_s | A_rest] -> LDS (row tt at Wp + tt*nb), 8 loads in flight
+    for (int base = 0; base < ws * nb; base += 8 * kPThreads) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + t + u * kPThreads;
+        x[u] = idx < ws * nb ? p.red[idx] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + t + u * kPThreads;
+        if (idx < ws * nb) Wp[idx] = x[u];
+      }
+    }
+    for (int idx = ws * nb + t; idx < W * nb; idx += kPThreads) Wp[idx] = 0.0;   // rows ws .. W of a ragged slab
     __syncthreads();
     // Gram rows -> S (column j = cs + tt holds v_q^T v_j for q < cs + ws)
     if (wg == 0)
@@ -276,57 +300,98 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         p.S[q + (int64_t)(cs + tt) * nb] = Wp[tt * nb + q];
       }
     // T_s by the recurrence T(r, tt) = -tau_tt sum_{r<=u<tt} T(r, u) v_u^T v_tt,
-    // which involves only row r: thread r builds its row without barriers
+    // which involves only row r: lane r of wave 0 keeps its row in registers
+    // (entries left of the diagonal are zero, so the sums can run over u < tt)
     if (t < W) {
       const int r = t;
+      double tr[W];
+#pragma unroll
       for (int tt = 0; tt < W; ++tt) {
-        double val = 0.0;
-        if (r < ws && tt < ws) {
-          if (tt == r) {
-            val = taus[tt];
-          } else if (tt > r) {
-            double acc = 0.0;
-            for (int u = r; u < tt; ++u) acc += Ts[r + u * W] * Wp[u * nb + cs + tt];
-            val = -taus[tt] * acc;
-          }
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < tt; u += 2) {
+          a0 += tr[u] * Wp[u * nb + cs + tt];
+          if (u + 1 < tt) a1 += tr[u + 1] * Wp[(u + 1) * nb + cs + tt];
         }
-        Ts[r + tt * W] = val;
+        const double ta = taus[tt];
+        const bool live = r < ws && tt < ws && tt >= r;
+        tr[tt] = !live ? 0.0 : (tt == r ? ta : -ta * (a0 + a1));
+        __asm__ volatile("" ::: "memory");   // keep the loads of later steps from piling up in registers
       }
+#pragma unroll
+      for (int tt = 0; tt < W; ++tt) Ts[r + tt * W] = tr[tt];
     }
     __syncthreads();
     const int rest = nb - (cs + ws);
     if (rest > 0) {
-      // Wp(:, rest) <- T_s^T (V_s^T A_rest) in place: one thread per column,
-      // rows from the last up (row tt only needs rows <= tt)
-      for (int c = cs + ws + t; c < nb; c += kPThreads)
-        for (int tt = ws - 1; tt >= 0; --tt) {
-          double acc = 0.0;
-          for (int u = 0; u <= tt; ++u) acc += Ts[u + tt * W] * Wp[u * nb + c];
-          Wp[tt * nb + c] = acc;
-        }
-      __syncthreads();
-      // A_rest(own rows) -= V_s Wp on the matrix cores, computed transposed
-      // (D[i][j] = sum_tt Wp(tt, c0 + i) V_s(r0 + j, tt)) so that each lane
-      // holds consecutive rows of one column of P: 16 x 16 blocks dealt to waves
+      // A_rest -= V_s (T_s^T W) is applied as (V_s T_s^T) W: X <- X T_s^T on
+      // the matrix cores, one wave per 16-row block (it reads all its rows
+      // before writing them, so the update is in place), W stays as reduced
       {
-        const int rb = (nrow + 15) / 16, cb = (rest + 15) / 16;
-        for (int blk = wave; blk < rb * cb; blk += kPThreads / 64) {
-          const int r0 = 16 * (blk % rb), c0 = 16 * (blk / rb);
-          d4 acc = {0.0, 0.0, 0.0, 0.0};
-          const int ca = cs + ws + min(c0 + li, rest - 1);
-          for (int k0 = 0; k0 < ws; k0 += 4) {
-            const int tt = k0 + lk;
-            const double a = tt < ws ? Wp[tt * nb + ca] : 0.0;
-            const double bv = X[tt * ldx + min(r0 + li, rpw4 - 1)];   // zero for tt >= ws and pad rows
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        const int rb = (nrow + 15) / 16;
+        for (int blk = wave; blk < rb; blk += kPThreads / 64) {
+          const int r0 = 16 * blk;
+          const int ra = min(r0 + li, rpw4 - 1);
+          d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int k0 = 0; k0 < W; k0 += 4) {
+            const double a = X[(k0 + lk) * ldx + ra];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[li + (k0 + lk) * W], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[16 + li + (k0 + lk) * W], acc1, 0, 0, 0);
           }
-          const int r = r0 + li;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int c = c0 + 4 * q + lk;
-            if (r < nrow && c < rest) {
-              double *ap = p.P + (rbeg + r) + (int64_t)(cs + ws + c) * p.ldp;
-              *ap -= acc[q];
+            const int r = r0 + 4 * q + lk;
+            if (r < nrow) {
+              X[li * ldx + r] = acc0[q];
+              X[(16 + li) * ldx + r] = acc1[q];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // A_rest(own rows) -= (V_s T_s^T) W on the matrix cores, computed transposed
+      // (D[i][j] = sum_tt W(tt, c0 + i) X(r0 + j, tt)) so that each lane
+      // holds consecutive rows of one column of P: 16 x 16 blocks dealt to waves
+      {
+        // four blocks per pass: their 16 loads of P are issued before the MFMAs
+        const int rb = (nrow + 15) / 16, cb = (rest + 15) / 16, nblk = rb * cb;
+        constexpr int NW = kPThreads / 64, GB = 4;
+        for (int b0 = wave * GB; b0 < nblk; b0 += NW * GB) {
+          double pv[GB][4];
+          d4 acc[GB];
+#pragma unroll
+          for (int u = 0; u < GB; ++u) {
+            const int blk = b0 + u;
+            const int r = 16 * (blk % rb) + li, c0 = 16 * (blk / rb);
+            acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int c = c0 + 4 * q + lk;
+              pv[u][q] = (blk < nblk && r < nrow && c < rest) ? p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] : 0.0;
+            }
+          }
+          for (int k0 = 0; k0 < ws; k0 += 4) {
+            const int tt = k0 + lk;
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+              const int blk = min(b0 + u, nblk - 1);
+              const int r0 = 16 * (blk % rb), c0 = 16 * (blk / rb);
+              const int ca = cs + ws + min(c0 + li, rest - 1);
+              const double a = tt < ws ? Wp[tt * nb + ca] : 0.0;
+              const double bv = X[tt * ldx + min(r0 + li, rpw4 - 1)];   // zero for tt >= ws and pad rows
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < GB; ++u) {
+            const int blk = b0 + u;
+            const int r = 16 * (blk % rb) + li, c0 = 16 * (blk / rb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int c = c0 + 4 * q + lk;
+              if (blk < nblk && r < nrow && c < rest)
+                p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] = pv[u][q] - acc[u][q];
             }
           }
         }
