@@ -110,16 +110,16 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         const int e = t & 63, grp = t >> 6;
         const bool valid = (e < W) ? (e < E) : (e - W < E);
         double acc = 0.0;
-        // loads issued 8 at a time, summed in workgroup order
-        for (int w0 = grp; w0 < nwg; w0 += 32) {
-          double x[8];
+        // loads issued 16 at a time (one round trip at 64 workgroups), summed in workgroup order
+        for (int w0 = grp; w0 < nwg; w0 += 64) {
+          double x[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const int w2 = w0 + 4 * u;
             x[u] = (valid && w2 < nwg) ? part_cs[((size_t)buf * nwg + w2) * 2 * W + e] : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc += x[u];
+          for (int u = 0; u < 16; ++u) acc += x[u];
         }
         sc[grp * 64 + e] = acc;
         __syncthreads();

@@ -390,7 +390,9 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
       }
       const double d = gsum(d0 + d1);
       const double f = act ? tau * d : 0.0;
-      __asm__ volatile("" ::: "memory");   // re-read v below rather than hold it in registers
+      // up to 40 rows per lane v stays in registers between the two loops;
+      // beyond that it would spill, so the update re-reads it from LDS
+      if constexpr (RPL > 40) __asm__ volatile("" ::: "memory");
 #pragma unroll
       for (int i = 0; i < RPL; ++i) y[i] -= f * v[sub + kRLanes * i];
     }
