@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run (profiling)")
     ap.add_argument("--no-residual", action="store_true", help="skip the residual check (profiling)")
     ap.add_argument("--cpu-blocks", type=int, default=2, help="oracle sample: leading blocks factored on the CPU")
+    ap.add_argument("--no-bwd", action="store_true", help="skip the bwd/fwd ratio measurement (C5)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain copy-like kernel (torch.neg) over 2^26 doubles, to scale HBM counters")
     return ap.parse_args()
@@ -94,6 +95,60 @@ def cpu_baseline(A_host, w, nblocks):
             "sample": f"first {nblocks} blocks (rank {k}) of the {w.name} factorization, {dt:.1f} s wall; "
                       f"normalised by the Householder-QR flops of those {k} columns",
             "seconds": dt}
+
+
+def bwd_fwd_ratio(reps=5):
+    """bwd/fwd of the truncated factorization on C5 (4096^2 FP64, b = 128,
+    p = 10, k = 256): fwd = factor(rank = k) + lowrank; bwd = lowrank_backward
+    with the forward's factors kept, or with recompute (a fixed-pivot
+    refactorization, no sketch, then lowrank_backward).  Medians of `reps`
+    HIP-event timings; the Python wrappers allocate their outputs and
+    workspaces through torch's caching allocator inside the timed calls."""
+    import numpy as np
+    import torch
+
+    import paper_1505_08115_amd as R
+    import workloads as W
+    w = W.WORKLOADS["C5"]
+    dev = torch.device("cuda:0")
+    A = R.colmajor(W.workload_matrix(w, device=dev))
+    k = w.rank
+    g = torch.Generator(device="cpu").manual_seed(55)
+    Gbar = R.colmajor(torch.randn(w.m, w.n, generator=g, dtype=torch.float64).to(dev))
+
+    def timed(fn):
+        out = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out[1:]))          # the first call warms up
+
+    state = {}
+
+    def fwd():
+        state["Fz"] = R.factor(A, block=w.b, oversample=w.p, seed=w.seed, rank=k)
+        state["Ak"] = R.lowrank(state["Fz"], k)
+
+    def bwd():
+        state["dA"] = R.lowrank_backward(A, state["Fz"], Gbar, k)
+
+    def bwd_recompute():
+        Fz2 = R.factor(A, block=w.b, oversample=0, rank=k, jpvt=state["Fz"].jpvt)
+        state["dA2"] = R.lowrank_backward(A, Fz2, Gbar, k)
+
+    tf = timed(fwd)
+    tb = timed(bwd)
+    tr = timed(bwd_recompute)
+    agree = float(torch.linalg.norm(state["dA2"] - state["dA"]) / torch.linalg.norm(state["dA"]))
+    return {"workload": f"C5: {w.m}x{w.n} FP64, b={w.b}, p={w.p}, k={k}", "fwd_ms": tf, "bwd_ms": tb,
+            "bwd_recompute_ms": tr, "ratio": tb / tf, "ratio_recompute": tr / tf,
+            "recompute_vs_kept_rel_diff": agree, "dtype": "f64",
+            "note": "FP32 storage is not supported by the truncation and backward in this build"}
 
 
 def main():
@@ -208,6 +263,8 @@ def main():
         "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "latency": latency,
                   "mixed": mixed},
     }
+    if not args.no_bwd:
+        out["extra"]["bwd_fwd"] = bwd_fwd_ratio()
     if args.calibrate:
         # 512 MiB read + 512 MiB written by one elementwise kernel
         x = torch.rand(1 << 26, dtype=torch.float64, device=dev)

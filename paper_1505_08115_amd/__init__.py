@@ -128,8 +128,11 @@ def _ptr(t):
 
 
 def colmajor(t):
-    """A column-major (stride(0) == 1) copy of a 2-D tensor."""
-    return t.t().contiguous().t()
+    """A column-major (stride(0) == 1) copy of a 2-D tensor (always a new tensor)."""
+    m, n = t.shape
+    out = torch.empty_strided((m, n), (1, max(1, m)), dtype=t.dtype, device=t.device)
+    out.copy_(t)
+    return out
 
 
 def _ld(t):

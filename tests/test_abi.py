@@ -93,3 +93,11 @@ def test_work_byte_queries_are_host_only_and_positive(lib):
     assert lib.rqrcp_lowrank_work_bytes(0, 4096, 4096, 256, 128) > 0
     assert lib.rqrcp_lowrank_backward_work_bytes(0, 4096, 4096, 256, 128) > 0
     assert lib.rqrcp_lowrank_work_bytes(0, 0, 4096, 256, 128) == 0     # invalid sizes report 0
+
+
+def test_colmajor_always_copies():
+    a = torch.randn(5, 3, dtype=torch.float64)
+    c = R.colmajor(a)
+    c2 = R.colmajor(c)                     # already column-major: still a new tensor
+    assert c.stride(0) == 1 and c2.stride(0) == 1
+    assert c2.data_ptr() != c.data_ptr() and torch.equal(c2, a)

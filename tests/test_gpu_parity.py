@@ -146,6 +146,15 @@ def test_factor_draws_the_same_sketch_as_the_oracle(m, n, b, p):
     _invariants(A, Fz)
 
 
+def test_factor_leaves_a_column_major_input_unchanged():
+    A = R.colmajor(torch.randn(300, 200, dtype=torch.float64, device=DEV))
+    A0 = A.clone()
+    Fz = R.factor(A, block=32, oversample=4, seed=3)
+    torch.cuda.synchronize()
+    assert torch.equal(A, A0)
+    assert Fz.F.data_ptr() != A.data_ptr()
+
+
 def test_C1_full_parity():
     w = W.WORKLOADS["C1"]
     A = W.workload_matrix(w).numpy()
