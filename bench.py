@@ -97,7 +97,7 @@ def cpu_baseline(A_host, w, nblocks):
             "seconds": dt}
 
 
-def bwd_fwd_ratio(reps=5):
+def bwd_fwd_ratio(reps=5, dtype=None):
     """bwd/fwd of the truncated factorization on C5 (4096^2 FP64, b = 128,
     p = 10, k = 256): fwd = factor(rank = k) + lowrank; bwd = lowrank_backward
     with the forward's factors kept, or with recompute (a fixed-pivot
@@ -111,10 +111,11 @@ def bwd_fwd_ratio(reps=5):
     import workloads as W
     w = W.WORKLOADS["C5"]
     dev = torch.device("cuda:0")
-    A = R.colmajor(W.workload_matrix(w, device=dev))
+    dtype = dtype or torch.float64
+    A = R.colmajor(W.workload_matrix(w, device=dev).to(dtype))
     k = w.rank
     g = torch.Generator(device="cpu").manual_seed(55)
-    Gbar = R.colmajor(torch.randn(w.m, w.n, generator=g, dtype=torch.float64).to(dev))
+    Gbar = R.colmajor(torch.randn(w.m, w.n, generator=g, dtype=torch.float64).to(dev).to(dtype))
 
     def timed(fn):
         out = []
@@ -145,10 +146,10 @@ def bwd_fwd_ratio(reps=5):
     tb = timed(bwd)
     tr = timed(bwd_recompute)
     agree = float(torch.linalg.norm(state["dA2"] - state["dA"]) / torch.linalg.norm(state["dA"]))
-    return {"workload": f"C5: {w.m}x{w.n} FP64, b={w.b}, p={w.p}, k={k}", "fwd_ms": tf, "bwd_ms": tb,
+    name = "FP64" if dtype == torch.float64 else "FP32 storage (FP32 factorization, FP64 truncation/backward)"
+    return {"workload": f"C5: {w.m}x{w.n} {name}, b={w.b}, p={w.p}, k={k}", "fwd_ms": tf, "bwd_ms": tb,
             "bwd_recompute_ms": tr, "ratio": tb / tf, "ratio_recompute": tr / tf,
-            "recompute_vs_kept_rel_diff": agree, "dtype": "f64",
-            "note": "FP32 storage is not supported by the truncation and backward in this build"}
+            "recompute_vs_kept_rel_diff": agree, "dtype": "f64" if dtype == torch.float64 else "f32"}
 
 
 def main():
@@ -265,6 +266,7 @@ def main():
     }
     if not args.no_bwd:
         out["extra"]["bwd_fwd"] = bwd_fwd_ratio()
+        out["extra"]["bwd_fwd_fp32"] = bwd_fwd_ratio(dtype=torch.float32)
     if args.calibrate:
         # 512 MiB read + 512 MiB written by one elementwise kernel
         x = torch.rand(1 << 26, dtype=torch.float64, device=dev)

@@ -146,7 +146,9 @@ rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64
  * applied in WY form as Section 5.1 asks).  VR, ldvr: the factored A (only
  * the Householder vectors below the diagonal of its first k columns are
  * read); T as written by rqrcp_factor; k, b as used there.  C has the storage
- * type dt.  work: at least rqrcp_apply_q_work_bytes bytes.
+ * type dt; with dt = F32 the operands are widened to FP64 in the workspace,
+ * the products run in FP64 and C is rounded back to FP32.  work: at least
+ * rqrcp_apply_q_work_bytes bytes.
  * Errors: RQRCP_ERR_ARG, RQRCP_ERR_WORKSPACE, RQRCP_ERR_HIP. */
 size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t k, int64_t b, int64_t ncol);
 rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t m, int64_t k,
@@ -156,7 +158,8 @@ rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
 /* Apply P or P^T from the right to C (nrow x n, ld ldc >= nrow):
  * trans = 0: C <- C P;  trans = 1: C <- C P^T.  PERM (S == NULL): a column
  * permutation by jpvt ((C P)(:, j) = C(:, jpvt[j])).  ORTHO: the product of
- * the S blocks (k, b as in the factorization).  work: at least
+ * the S blocks (k, b as in the factorization).  C has the storage type dt
+ * (F32: computed in FP64 on a widened copy).  work: at least
  * rqrcp_apply_p_work_bytes bytes. */
 size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t dt, int64_t nrow, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t nrow, int64_t n,
@@ -167,7 +170,8 @@ rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
  * definition; Section 6.1 for its error ||R_22||).  Inputs as written by
  * rqrcp_factor with rank kf >= k (VR, ldvr, jpvt, T, S); kf fixes how many
  * blocks of T and S exist (P is the product of all kf/b S blocks).  Ak (out)
- * m x n, ld ldak >= m, type dt.  work: at least rqrcp_lowrank_work_bytes. */
+ * m x n, ld ldak >= m, type dt (F32: VR is widened to FP64, the products run
+ * in FP64 and A_k is rounded to FP32).  work: at least rqrcp_lowrank_work_bytes. */
 size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k,
                              int64_t kf, int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt,
@@ -182,7 +186,8 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
  *   Z  = (I - Pi) [dAk P R_k^T + A dAk^T Q_k] R_11^{-T}.
  * Permutation form only.  A (in) the ORIGINAL input, ld lda.  VR, ldvr, jpvt,
  * T: a factorization of A with rank >= k (e.g. recomputed with fixed_pivots).
- * dAk (in) m x n, ld ldg; dA (out) m x n, ld ldda.  All of type dt.
+ * dAk (in) m x n, ld ldg; dA (out) m x n, ld ldda.  All of type dt (F32:
+ * widened to FP64 in the workspace, computed in FP64, dA rounded to FP32).
  * work: at least rqrcp_lowrank_backward_work_bytes bytes. */
 size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n,

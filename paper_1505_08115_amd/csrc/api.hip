@@ -654,7 +654,14 @@ rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64
 // ---------------------------------------------------------------------------
 // Q, P, truncation and the backward pass
 
-size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t, int64_t m, int64_t k, int64_t b, int64_t ncol) {
+// FP32 storage in the products below: the FP32 operands are widened into FP64
+// copies at the front of the workspace, the FP64 sequence runs on them and the
+// results are rounded back (FP32 storage, FP64 arithmetic).
+static size_t shadow_bytes(rqrcp_dtype_t dt, size_t doubles) {
+  return dt == RQRCP_F32 ? ((doubles * 8 + 255) / 256) * 256 : 0;
+}
+
+static size_t apply_q_work_f64(int64_t m, int64_t k, int64_t b, int64_t ncol) {
   if (m < 1 || k < 1 || b < 1 || ncol < 0) return 0;
   size_t gp = 0;
   for (int64_t r0 = 0; r0 < k; r0 += b) {
@@ -669,6 +676,12 @@ size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t, int64_t m, int64_t k, int64_t b, 
   w.take((size_t)b * ncol * 8);
   w.take(gp * 8);
   return w.off + 256;
+}
+
+size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t k, int64_t b, int64_t ncol) {
+  const size_t base = apply_q_work_f64(m, k, b, ncol);
+  if (base == 0) return 0;
+  return shadow_bytes(dt, (size_t)m * k) + shadow_bytes(dt, (size_t)m * ncol) + base;
 }
 
 static rqrcp_status_t apply_q_impl(rqrcp_handle_t h, int trans, int64_t m, int64_t k, int64_t b, const double *VR,
@@ -708,7 +721,7 @@ rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
                              const void *VR, int64_t ldvr, const double *T, int64_t ncol, void *C, int64_t ldc,
                              void *work, size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
-  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
   if (m < 1 || k < 1 || k > m || b < 1) return fail(h, RQRCP_ERR_ARG, "need 1 <= k <= m and b >= 1");
   if (!VR || !T || !C) return fail(h, RQRCP_ERR_ARG, "VR, T and C must not be NULL");
@@ -717,11 +730,22 @@ rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
   if (ncol == 0) return RQRCP_OK;
   if (!work || work_bytes < rqrcp_apply_q_work_bytes(dt, m, k, b, ncol))
     return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_q_work_bytes");
-  return apply_q_impl(h, trans, m, k, b, static_cast<const double *>(VR), ldvr, T, ncol, static_cast<double *>(C), ldc,
-                      work);
+  if (dt == RQRCP_F64)
+    return apply_q_impl(h, trans, m, k, b, static_cast<const double *>(VR), ldvr, T, ncol, static_cast<double *>(C),
+                        ldc, work);
+  hipStream_t s = h->stream;
+  Bump w;
+  double *V64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * k)));
+  double *C64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * ncol)));
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, V64, m, m, k), "V to FP64");
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(C), ldc, C64, m, m, ncol), "C to FP64");
+  rqrcp_status_t st = apply_q_impl(h, trans, m, k, b, V64, m, T, ncol, C64, m, at<void>(work, w.off));
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, C64, m, static_cast<float *>(C), ldc, m, ncol), "C to FP32");
+  return RQRCP_OK;
 }
 
-size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t, int64_t nrow, int64_t n, int64_t k, int64_t b) {
+static size_t apply_p_work_f64(int64_t nrow, int64_t n, int64_t k, int64_t b) {
   if (nrow < 0 || n < 1 || b < 1) return 0;
   size_t gp = 0;
   for (int64_t r0 = 0; r0 < k; r0 += b) {
@@ -736,6 +760,12 @@ size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t, int64_t nrow, int64_t n, int64_t 
   w.take((size_t)nrow * b * 8);
   w.take(gp * 8);
   return w.off + 256;
+}
+
+size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t dt, int64_t nrow, int64_t n, int64_t k, int64_t b) {
+  const size_t base = apply_p_work_f64(nrow, n, k, b);
+  if (base == 0) return 0;
+  return shadow_bytes(dt, (size_t)nrow * n) + base;
 }
 
 static rqrcp_status_t apply_p_impl(rqrcp_handle_t h, int trans, int64_t nrow, int64_t n, int64_t k, int64_t b,
@@ -784,7 +814,7 @@ rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
                              int64_t b, const int32_t *jpvt, const double *S, void *C, int64_t ldc, void *work,
                              size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
-  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
+  if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
   if (nrow < 0 || n < 1 || b < 1 || k < 1 || k > n) return fail(h, RQRCP_ERR_ARG, "need nrow >= 0, 1 <= k <= n, b >= 1");
   if (!C || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "C and one of jpvt / S must be given");
@@ -792,17 +822,31 @@ rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
   if (nrow == 0) return RQRCP_OK;
   if (!work || work_bytes < rqrcp_apply_p_work_bytes(dt, nrow, n, k, b))
     return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_p_work_bytes");
-  return apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, static_cast<double *>(C), ldc, work);
+  if (dt == RQRCP_F64) return apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, static_cast<double *>(C), ldc, work);
+  hipStream_t s = h->stream;
+  Bump w;
+  double *C64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)nrow * n)));
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(C), ldc, C64, nrow, nrow, n), "C to FP64");
+  rqrcp_status_t st = apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, C64, nrow, at<void>(work, w.off));
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, C64, nrow, static_cast<float *>(C), ldc, nrow, n), "C to FP32");
+  return RQRCP_OK;
 }
 
-size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+static size_t lowrank_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
   if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
   Bump w;
   w.take((size_t)m * k * 8);                               // Q_k
   w.take((size_t)k * n * 8);                               // R_k P^T
-  w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k), rqrcp_apply_p_work_bytes(dt, k, n, n, b)));
+  w.take(std::max(apply_q_work_f64(m, k, b, k), apply_p_work_f64(k, n, n, b)));
   w.take(gemm_part_doubles(m, n, k) * 8);
   return w.off + 256;
+}
+
+size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+  const size_t base = lowrank_work_f64(m, n, k, b);
+  if (base == 0) return 0;
+  return 2 * shadow_bytes(dt, (size_t)m * n) + base;       // VR and A_k in FP64
 }
 
 static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t b, const double *VR, int64_t ldvr,
@@ -811,24 +855,14 @@ static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t b,
   return apply_q_impl(h, 0, m, k, b, VR, ldvr, T, k, Qk, m, work);
 }
 
-rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t kf,
-                             int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T,
-                             const double *S, void *Ak, int64_t ldak, void *work, size_t work_bytes) {
-  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
-  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
-  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
-  if (kf < k || kf > n) return fail(h, RQRCP_ERR_ARG, "kf (rank of the factorization) must satisfy k <= kf <= n");
-  if (!VR || !T || !Ak || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "VR, T, Ak and jpvt (or S) are required");
-  if (ldvr < m || ldak < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldak must be >= m");
-  if (!work || work_bytes < rqrcp_lowrank_work_bytes(dt, m, n, k, b))
-    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_work_bytes");
+static rqrcp_status_t lowrank_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t kf, int64_t b,
+                                   const double *F, int64_t ldvr, const int32_t *jpvt, const double *T,
+                                   const double *S, double *Ak, int64_t ldak, void *work) {
   hipStream_t s = h->stream;
-  const double *F = static_cast<const double *>(VR);
   Bump w;
   double *Qk = at<double>(work, w.take((size_t)m * k * 8));
   double *RP = at<double>(work, w.take((size_t)k * n * 8));
-  void *sub = at<void>(work, w.take(std::max(rqrcp_apply_q_work_bytes(dt, m, k, b, k),
-                                             rqrcp_apply_p_work_bytes(dt, k, n, k, b))));
+  void *sub = at<void>(work, w.take(std::max(apply_q_work_f64(m, k, b, k), apply_p_work_f64(k, n, n, b))));
   double *part = at<double>(work, w.take(gemm_part_doubles(m, n, k) * 8));
   // R_k P^* (k x n)
   CHK(launch_extract_r(s, F, ldvr, k, n, RP, k), "extract R_k");
@@ -836,12 +870,37 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
   if (st != RQRCP_OK) return st;
   st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
   if (st != RQRCP_OK) return st;
-  GemmF64 g{false, false, m, n, k, Qk, m, RP, k, static_cast<double *>(Ak), ldak, 1.0, 0.0};
+  GemmF64 g{false, false, m, n, k, Qk, m, RP, k, Ak, ldak, 1.0, 0.0};
   CHK(launch_gemm_f64(s, g, part), "Q_k (R_k P^*)");
   return RQRCP_OK;
 }
 
-size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t kf,
+                             int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T,
+                             const double *S, void *Ak, int64_t ldak, void *work, size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
+  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (kf < k || kf > n) return fail(h, RQRCP_ERR_ARG, "kf (rank of the factorization) must satisfy k <= kf <= n");
+  if (!VR || !T || !Ak || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "VR, T, Ak and jpvt (or S) are required");
+  if (ldvr < m || ldak < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldak must be >= m");
+  if (!work || work_bytes < rqrcp_lowrank_work_bytes(dt, m, n, k, b))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_work_bytes");
+  if (dt == RQRCP_F64)
+    return lowrank_impl(h, m, n, k, kf, b, static_cast<const double *>(VR), ldvr, jpvt, T, S,
+                        static_cast<double *>(Ak), ldak, work);
+  hipStream_t s = h->stream;
+  Bump w;
+  double *F64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  double *Ak64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, F64, m, m, n), "VR to FP64");
+  rqrcp_status_t st = lowrank_impl(h, m, n, k, kf, b, F64, m, jpvt, T, S, Ak64, m, at<void>(work, w.off));
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, Ak64, m, static_cast<float *>(Ak), ldak, m, n), "A_k to FP32");
+  return RQRCP_OK;
+}
+
+static size_t backward_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
   if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
   Bump w;
   w.take((size_t)m * k * 8);   // Q_k
@@ -852,7 +911,7 @@ size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n,
   w.take((size_t)k * k * 8);   // R_11^{-1}
   w.take((size_t)m * k * 8);   // Z
   w.take((size_t)k * n * 8);   // Q_k^T Gbar
-  w.take(rqrcp_apply_q_work_bytes(dt, m, k, b, k));
+  w.take(apply_q_work_f64(m, k, b, k));
   size_t gp = 0;
   gp = std::max(gp, gemm_part_doubles(m, k, n));
   gp = std::max(gp, gemm_part_doubles(n, k, m));
@@ -864,22 +923,16 @@ size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n,
   return w.off + 256;
 }
 
-rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
-                                      const void *Av, int64_t lda, const void *VR, int64_t ldvr, const int32_t *jpvt,
-                                      const double *T, const void *dAkv, int64_t ldg, void *dAv, int64_t ldda,
-                                      void *work, size_t work_bytes) {
-  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
-  if (dt != RQRCP_F64) return fail(h, RQRCP_ERR_UNSUPPORTED, "dt: only F64 in this build");
-  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
-  if (!Av || !VR || !jpvt || !T || !dAkv || !dAv) return fail(h, RQRCP_ERR_ARG, "a required pointer is NULL");
-  if (lda < m || ldvr < m || ldg < m || ldda < m) return fail(h, RQRCP_ERR_ARG, "leading dimensions must be >= m");
-  if (!work || work_bytes < rqrcp_lowrank_backward_work_bytes(dt, m, n, k, b))
-    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_backward_work_bytes");
+size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
+  const size_t base = backward_work_f64(m, n, k, b);
+  if (base == 0) return 0;
+  return 4 * shadow_bytes(dt, (size_t)m * n) + base;       // A, VR, dA_k and dA in FP64
+}
+
+static rqrcp_status_t backward_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t b, const double *A,
+                                    int64_t lda, const double *F, int64_t ldvr, const int32_t *jpvt, const double *T,
+                                    const double *Gb, int64_t ldg, double *dA, int64_t ldda, void *work) {
   hipStream_t s = h->stream;
-  const double *A = static_cast<const double *>(Av);
-  const double *F = static_cast<const double *>(VR);
-  const double *Gb = static_cast<const double *>(dAkv);
-  double *dA = static_cast<double *>(dAv);
   Bump w;
   double *Qk = at<double>(work, w.take((size_t)m * k * 8));
   double *Rk = at<double>(work, w.take((size_t)k * n * 8));
@@ -889,7 +942,7 @@ rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_
   double *Ri = at<double>(work, w.take((size_t)k * k * 8));
   double *Z = at<double>(work, w.take((size_t)m * k * 8));
   double *KN = at<double>(work, w.take((size_t)k * n * 8));
-  void *sub = at<void>(work, w.take(rqrcp_apply_q_work_bytes(dt, m, k, b, k)));
+  void *sub = at<void>(work, w.take(apply_q_work_f64(m, k, b, k)));
   size_t gp = 0;
   gp = std::max(gp, gemm_part_doubles(m, k, n));
   gp = std::max(gp, gemm_part_doubles(n, k, m));
@@ -927,6 +980,35 @@ rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_
   GemmF64 g8{false, false, m, n, k, Qk, m, KN, k, dA, ldda, 1.0, 0.0};
   CHK(launch_gemm_f64(s, g8, part), "Q_k (Q_k^T Gbar)");
   CHK(launch_scatter_cols(s, Z, m, m, jpvt, k, dA, ldda, n, true), "scatter Z");
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
+                                      const void *Av, int64_t lda, const void *VR, int64_t ldvr, const int32_t *jpvt,
+                                      const double *T, const void *dAkv, int64_t ldg, void *dAv, int64_t ldda,
+                                      void *work, size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
+  if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (!Av || !VR || !jpvt || !T || !dAkv || !dAv) return fail(h, RQRCP_ERR_ARG, "a required pointer is NULL");
+  if (lda < m || ldvr < m || ldg < m || ldda < m) return fail(h, RQRCP_ERR_ARG, "leading dimensions must be >= m");
+  if (!work || work_bytes < rqrcp_lowrank_backward_work_bytes(dt, m, n, k, b))
+    return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_backward_work_bytes");
+  if (dt == RQRCP_F64)
+    return backward_impl(h, m, n, k, b, static_cast<const double *>(Av), lda, static_cast<const double *>(VR), ldvr,
+                         jpvt, T, static_cast<const double *>(dAkv), ldg, static_cast<double *>(dAv), ldda, work);
+  hipStream_t s = h->stream;
+  Bump w;
+  double *A64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  double *F64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  double *G64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  double *D64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(Av), lda, A64, m, m, n), "A to FP64");
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, F64, m, m, n), "VR to FP64");
+  CHK(launch_copy_f32_f64(s, static_cast<const float *>(dAkv), ldg, G64, m, m, n), "dA_k to FP64");
+  rqrcp_status_t st = backward_impl(h, m, n, k, b, A64, m, F64, m, jpvt, T, G64, m, D64, m, at<void>(work, w.off));
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, D64, m, static_cast<float *>(dAv), ldda, m, n), "dA to FP32");
   return RQRCP_OK;
 }
 

@@ -405,3 +405,52 @@ def test_fp32_ortho_and_truncated():
             AP = torch.tensor(A32.astype(np.float64) @ P, device=DEV)
             res = torch.linalg.norm(AP - Q @ torch.triu(F[:k, :])) / torch.linalg.norm(A)
         assert float(res) <= 1e-5, f"{pivot}: residual {float(res):.3e}"
+
+
+def _widened(Fz):
+    """The same factorization with its storage widened to FP64."""
+    return R.Factorization(R.colmajor(Fz.F.double()), Fz.jpvt, Fz.tau, Fz.T, Fz.S, Fz.block, Fz.rank, Fz.pivot)
+
+
+@pytest.mark.parametrize("pivot", ["perm", "ortho"])
+def test_fp32_apply_q_apply_p_lowrank(pivot):
+    # FP32 storage: the products run in FP64 on widened copies, so the results
+    # are the FP64 entry points' results on the widened factors, rounded once
+    m, n, b, k = 300, 240, 32, 100
+    A32 = W.make_matrix(m, n, W.sigma_geometric(n, 4.0), seed=19).numpy().astype(np.float32)
+    Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=6, pivot=pivot, rank=k, seed=4)
+    F64 = _widened(Fz)
+    C = torch.tensor(W.gaussian_matrix(m, 17, seed=3).numpy(), device=DEV)
+    for trans in (False, True):
+        got = R.apply_q(Fz, R.colmajor(C.float()), trans=trans).double()
+        ref = R.apply_q(F64, R.colmajor(C.float().double()), trans=trans)
+        assert float(torch.max(torch.abs(got - ref))) <= 2 ** -23 * float(torch.max(torch.abs(ref))) * 2
+    D = torch.tensor(W.gaussian_matrix(9, n, seed=4).numpy(), device=DEV).float()
+    for trans in (False, True):
+        got = R.apply_p(Fz, R.colmajor(D), trans=trans).double()
+        ref = R.apply_p(F64, R.colmajor(D.double()), trans=trans)
+        assert float(torch.max(torch.abs(got - ref))) <= 2 ** -23 * float(torch.max(torch.abs(ref))) * 2
+    for kk in (k, 37):
+        got = R.lowrank(Fz, kk).double()
+        ref = R.lowrank(F64, kk)
+        assert float(torch.max(torch.abs(got - ref))) <= 2 ** -23 * float(torch.max(torch.abs(ref))) * 2
+    if pivot == "perm":
+        # and A_k is the projection of A onto its first k pivot columns (FP32-level agreement)
+        Ad = torch.tensor(A32.astype(np.float64), device=DEV)
+        Q, _ = torch.linalg.qr(Ad[:, Fz.jpvt[:k].long()])
+        Ak = R.lowrank(Fz, k).double()
+        assert float(torch.linalg.norm(Ak - Q @ (Q.T @ Ad)) / torch.linalg.norm(Ad)) <= 1e-5
+
+
+def test_fp32_lowrank_backward_matches_oracle_gradient():
+    m, n, k, b = 300, 300, 64, 32
+    A32 = W.make_matrix(m, n, W.sigma_geometric(n, 3.0), seed=m).numpy().astype(np.float32)
+    B = W.gaussian_matrix(m, n, seed=n).numpy()
+    Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=5, seed=7, rank=k)
+    jp = Fz.jpvt.cpu().numpy()
+    Ak = R.lowrank(Fz, k).double()
+    Gbar = (2 * (Ak - torch.tensor(B, device=DEV))).float()
+    dA = R.lowrank_backward(R.colmajor(torch.tensor(A32, device=DEV)), Fz, R.colmajor(Gbar), k).double().cpu().numpy()
+    ref = O.lowrank_grad(A32.astype(np.float64), jp, k, Gbar.double().cpu().numpy())
+    # the FP32 factors carry relative errors of a few 1e-7; the gradient inherits them
+    assert np.linalg.norm(dA - ref) <= 1e-4 * np.linalg.norm(ref)
