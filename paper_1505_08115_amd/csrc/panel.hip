@@ -45,16 +45,17 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   double *Zc = X + (size_t)W * ldx;         // W x ldz   staged columns
   double *Wp = Zc + (size_t)W * ldz;        // W x nb    reduced V_s^T [V_0..V_s | A_rest], row t at Wp + t*nb
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
-  double *sc = Ts + W * W;                  // 320       reduction scratch
-  double *taus = sc + 320;                  // W
-  __shared__ double s_beta, s_tau, s_scale;
+  double *sc = Ts + W * W;                  // 640       reduction scratch
+  double *taus = sc + 640;                  // W
+  __shared__ double s_beta, s_tau, s_scale, s_beta1, s_tau1, s_scale1, s_v0n, s_yj;
+  __shared__ int s_two;
 
   const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
   const int64_t rbeg = (int64_t)wg * rpw;
   const int nrow = (int)max((int64_t)0, min((int64_t)rpw, p.mi - rbeg));
   const int nslab = (nb + W - 1) / W;
-  double *part_cs = p.part;                                   // [2][nwg][2W]
-  double *part_up = p.part + (size_t)2 * nwg * 2 * W;         // [nwg][W*nb]
+  double *part_cs = p.part;                                   // [2][nwg][4W]
+  double *part_up = p.part + (size_t)2 * nwg * 4 * W;         // [nwg][W*nb]
   unsigned gen = 0;
   bool ok = true;
   int step = 0;
@@ -75,55 +76,85 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       X[c * ldx + r] = 0.0;
     }
     __syncthreads();
-    for (int jj = 0; jj < ws && ok; ++jj, ++step) {
+    for (int jj = 0; jj < ws && ok; ++step) {
       const int64_t j = cs + jj;
       const int E = ws - jj;
       const int buf = step & 1;
-      // partial sums of x_j^T x_c (own rows >= j) and x_c(j)
+      // Columns jj and jj+1 share one exchange when both lie in the slab and
+      // column jj+1 keeps at least two rows from its diagonal down.  H_j acts
+      // orthogonally on rows >= j, so (H_j x_{j+1})^T (H_j x_c) over those
+      // rows equals x_{j+1}^T x_c: the reflector of column j+1 and its action
+      // follow from the sums over rows >= j of x_j^T x_c and x_{j+1}^T x_c and
+      // the entries of rows j and j+1.
+      const bool pair = jj + 1 < ws && j + 2 < p.mi;
+      // partial sums over own rows >= j: [g0 | h0 | g1 | h1] at sc[0 .. 4W),
+      // g0_c = x_jj^T x_c, g1_c = x_{jj+1}^T x_c, h0_c = x_c(j), h1_c = x_c(j+1)
       {
         const int c = jj + (t >> 3), sub = t & 7;
-        double g = 0.0;
+        double g0 = 0.0, g1 = 0.0;
         if (c < ws) {
-          int r0 = (int)max((int64_t)0, j - rbeg);
-          for (int r = r0 + sub; r < nrow; r += 8) g += X[jj * ldx + r] * X[c * ldx + r];
+          const int r0 = (int)max((int64_t)0, j - rbeg);
+          if (pair) {
+            for (int r = r0 + sub; r < nrow; r += 8) {
+              const double xc = X[c * ldx + r];
+              g0 += X[jj * ldx + r] * xc;
+              g1 += X[(jj + 1) * ldx + r] * xc;
+            }
+          } else {
+            for (int r = r0 + sub; r < nrow; r += 8) g0 += X[jj * ldx + r] * X[c * ldx + r];
+          }
         }
-        g += __shfl_xor(g, 1, 64);
-        g += __shfl_xor(g, 2, 64);
-        g += __shfl_xor(g, 4, 64);
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+          g0 += __shfl_xor(g0, off, 64);
+          g1 += __shfl_xor(g1, off, 64);
+        }
         if (sub == 0 && c < ws) {
-          const double h = (j >= rbeg && j < rbeg + nrow) ? X[c * ldx + (int)(j - rbeg)] : 0.0;
-          sc[c - jj] = g;
-          sc[W + (c - jj)] = h;
+          const double h0 = (j >= rbeg && j < rbeg + nrow) ? X[c * ldx + (int)(j - rbeg)] : 0.0;
+          const double h1 = (j + 1 >= rbeg && j + 1 < rbeg + nrow) ? X[c * ldx + (int)(j + 1 - rbeg)] : 0.0;
+          sc[c - jj] = g0;
+          sc[W + (c - jj)] = h0;
+          sc[2 * W + (c - jj)] = g1;
+          sc[3 * W + (c - jj)] = h1;
         }
         __syncthreads();
-        // wave 0 publishes the 2E partial sums of this workgroup
-        if (t < 2 * W) {
-          const int e = t;
-          if ((e < W && e < E) || (e >= W && e - W < E))
-            part_cs[((size_t)buf * nwg + wg) * 2 * W + e] = sc[e];
+        // wave 0 publishes this workgroup's values (two per lane)
+        if (t < 64) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int e = t + 64 * q;
+            if (e % W < E && (q == 0 || pair)) part_cs[((size_t)buf * nwg + wg) * 4 * W + e] = sc[e];
+          }
         }
       }
       ok = grid_sync(gb, gen);
       if (!ok) break;
-      // fixed-order reduction: 4 groups of workgroups, then the groups in order
+      // fixed-order reduction: 4 groups of workgroups, then the groups in order;
+      // thread (grp, e) sums entries e and 64 + e
       {
         const int e = t & 63, grp = t >> 6;
-        const bool valid = (e < W) ? (e < E) : (e - W < E);
-        double acc = 0.0;
-        // loads issued 16 at a time (one round trip at 64 workgroups), summed in workgroup order
+        const bool v0 = e % W < E, v1 = pair && e % W < E;
+        double acc0 = 0.0, acc1 = 0.0;
+        // loads issued 32 at a time (one round trip at 64 workgroups), summed in workgroup order
         for (int w0 = grp; w0 < nwg; w0 += 64) {
-          double x[16];
+          double x0[16], x1[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int w2 = w0 + 4 * u;
-            x[u] = (valid && w2 < nwg) ? part_cs[((size_t)buf * nwg + w2) * 2 * W + e] : 0.0;
+            const double *src = part_cs + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 4 * W;
+            x0[u] = (v0 && w2 < nwg) ? src[e] : 0.0;
+            x1[u] = (v1 && w2 < nwg) ? src[64 + e] : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 16; ++u) acc += x[u];
+          for (int u = 0; u < 16; ++u) {
+            acc0 += x0[u];
+            acc1 += x1[u];
+          }
         }
-        sc[grp * 64 + e] = acc;
+        sc[grp * 128 + e] = acc0;
+        sc[grp * 128 + 64 + e] = acc1;
         __syncthreads();
-        if (t < 64) sc[t] = ((sc[t] + sc[64 + t]) + sc[128 + t]) + sc[192 + t];
+        if (t < 128) sc[t] = ((sc[t] + sc[128 + t]) + sc[256 + t]) + sc[384 + t];
         __syncthreads();
       }
       if (t == 0) {
@@ -139,29 +170,77 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
             beta = 0.0;
           }
         }
+        // column jj+1 after H_j: y = H_j x_{j+1}; its norm over rows > j is
+        // g1_{jj+1} - y(j)^2, taken only while the subtracted part is less
+        // than half (relative error below 2 u); otherwise a step of its own
+        int two = 0;
+        double beta1 = 0.0, tau1 = 0.0, scale1 = 1.0, v0n = 0.0, yj = 0.0;
+        if (pair && tau != 0.0) {
+          const double f01 = tau * ((sc[1] - beta * sc[W + 1]) / scale);
+          yj = sc[W + 1] - f01;
+          v0n = sc[3 * W] / scale;                      // v_j(j+1)
+          const double y1 = sc[3 * W + 1] - f01 * v0n;  // y(j+1)
+          const double g11 = sc[2 * W + 1];
+          const double n1 = g11 - yj * yj;
+          if (g11 > 0.0 && g11 < 1.79e308 && n1 > 0.5 * g11) {
+            two = 1;
+            beta1 = (y1 >= 0.0 ? -1.0 : 1.0) * sqrt(n1);
+            tau1 = (beta1 - y1) / beta1;
+            scale1 = y1 - beta1;
+          }
+        }
         s_beta = beta; s_tau = tau; s_scale = scale;
+        s_two = two; s_beta1 = beta1; s_tau1 = tau1; s_scale1 = scale1; s_v0n = v0n; s_yj = yj;
         taus[jj] = tau;
-        if (wg == 0) p.tau[j] = tau;
+        if (two) taus[jj + 1] = tau1;
+        if (wg == 0) {
+          p.tau[j] = tau;
+          if (two) p.tau[j + 1] = tau1;
+        }
       }
       __syncthreads();
       const double beta = s_beta, tau = s_tau, scale = s_scale;
-      // f_c = tau v^T x_c for the columns right of jj (index c - jj in sc[256..])
-      if (t > 0 && t < E) sc[256 + t] = tau * ((sc[t] - beta * sc[W + t]) / scale);
+      const int two = s_two;
+      // f0_c = tau v_j^T x_c at sc[512 + c - jj]; with a pair, f1_c =
+      // tau1 v_{j+1}^T (H_j x_c) at sc[576 + c - jj] for c > jj + 1
+      if (t > 0 && t < E) {
+        const double f0 = tau * ((sc[t] - beta * sc[W + t]) / scale);
+        sc[512 + t] = f0;
+        if (two && t > 1) {
+          const double zj = sc[W + t] - f0, zj1 = sc[3 * W + t] - f0 * s_v0n;
+          const double yz = sc[2 * W + t] - s_yj * zj;   // y^T z over rows > j
+          sc[576 + t] = s_tau1 * ((yz - s_beta1 * zj1) / s_scale1);
+        }
+      }
       __syncthreads();
+      const double beta1 = s_beta1, scale1 = s_scale1;
       for (int r = t; r < nrow; r += kPThreads) {
         const int64_t rg = rbeg + r;
         if (rg < j) continue;
         if (rg == j) {
           if (tau != 0.0)
-            for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[256 + c - jj];
+            for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[512 + c - jj];
           X[jj * ldx + r] = beta;
-        } else if (tau != 0.0) {
+          continue;
+        }
+        if (tau != 0.0) {
           const double vr = X[jj * ldx + r] / scale;
           X[jj * ldx + r] = vr;
-          for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[256 + c - jj] * vr;
+          for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[512 + c - jj] * vr;
+        }
+        if (two) {
+          if (rg == j + 1) {
+            for (int c = jj + 2; c < ws; ++c) X[c * ldx + r] -= sc[576 + c - jj];
+            X[(jj + 1) * ldx + r] = beta1;
+          } else {
+            const double vr1 = X[(jj + 1) * ldx + r] / scale1;
+            X[(jj + 1) * ldx + r] = vr1;
+            for (int c = jj + 2; c < ws; ++c) X[c * ldx + r] -= sc[576 + c - jj] * vr1;
+          }
         }
       }
       __syncthreads();
+      jj += two ? 2 : 1;
     }
     if (!ok) break;
     // write the slab back (R and the stored vectors) and the explicit V;
@@ -404,7 +483,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 
 size_t panel_lds_doubles(int rpw, int nb) {
   const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded strides
-  return (size_t)W * ld + (size_t)W * ld + (size_t)W * nb + W * W + 320 + W;
+  return (size_t)W * ld + (size_t)W * ld + (size_t)W * nb + W * W + 640 + W;
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
@@ -524,7 +603,7 @@ int panel_config(int64_t mi, int nb, int *rpw) {
   }
 }
 
-size_t panel_part_doubles(int nwg, int nb) { return (size_t)2 * nwg * 2 * W + (size_t)nwg * W * nb; }
+size_t panel_part_doubles(int nwg, int nb) { return (size_t)2 * nwg * 4 * W + (size_t)nwg * W * nb; }
 
 hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
   int rpw = 0;
