@@ -454,3 +454,29 @@ def test_fp32_lowrank_backward_matches_oracle_gradient():
     ref = O.lowrank_grad(A32.astype(np.float64), jp, k, Gbar.double().cpu().numpy())
     # the FP32 factors carry relative errors of a few 1e-7; the gradient inherits them
     assert np.linalg.norm(dA - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_panel_pairs_fallbacks_and_zero_columns():
+    # fixed pivots (the identity), so the panel sees the columns as given:
+    # column 1 nearly parallel to column 0 (the two-column step must fall back
+    # to single steps), column 9 exactly zero (tau = 0), b = 64 spans two slabs
+    m, n, b = 400, 160, 64
+    g = np.random.default_rng(12)
+    A = g.standard_normal((m, n))
+    A[:, 1] = A[:, 0] + 1e-6 * g.standard_normal(m)
+    A[:, 9] = 0.0
+    A[:, 40] = 3.0 * A[:, 39] - A[:, 38]      # exactly dependent on the two before it
+    jp = torch.arange(n, dtype=torch.int32)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=0, jpvt=jp)
+    torch.cuda.synchronize()
+    assert np.array_equal(Fz.jpvt.cpu().numpy(), np.arange(n))
+    _invariants(A, Fz)
+    # R is unique up to row signs for the leading full-rank columns (rows
+    # 0..39; column 40 is dependent, so the direction of row 40 is arbitrary);
+    # the nearly parallel pair amplifies rounding by about 1e6 in row 1
+    Rg = sign_rows(np.triu(Fz.F.cpu().numpy()[:40]))
+    Ro = sign_rows(np.linalg.qr(A, mode="r")[:40])
+    nA = np.linalg.norm(A)
+    assert np.max(np.abs(Rg - Ro)) <= 1e-8 * nA
+    taus = Fz.tau.cpu().numpy()
+    assert taus[9] == 0.0 and Rg[9, 9] == 0.0
