@@ -40,10 +40,9 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   extern __shared__ double lds[];
   const int nb = p.nb;
   const int rpw4 = (rpw + 3) & ~3;           // rows padded to the MFMA K step
-  const int ldx = rpw4 + 1, ldz = rpw4 + 1;  // odd strides: the 16 lanes of a fragment hit distinct banks
+  const int ldx = rpw4 + 1;                 // odd stride: the 16 lanes of a fragment hit distinct banks
   double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
-  double *Zc = X + (size_t)W * ldx;         // W x ldz   staged columns
-  double *Wp = Zc + (size_t)W * ldz;        // W x nb    reduced V_s^T [V_0..V_s | A_rest], row t at Wp + t*nb
+  double *Wp = X + (size_t)W * ldx;         // W x nb    reduced V_s^T [V_0..V_s | A_rest], row t at Wp + t*nb
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
   double *sc = Ts + W * W;                  // 640       reduction scratch
   double *taus = sc + 640;                  // W
@@ -272,52 +271,49 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     }
     __syncthreads();
     // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest], on the
-    // matrix cores: per 32-column chunk a 32 x 32 output, one 16 x 16 block
-    // per wave (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j] from
-    // lane j + 16k, D[i][j] in lane j + 16 (i%4), register i/4)
+    // matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j]
+    // from lane j + 16k, D[i][j] in lane j + 16 (i%4), register i/4).  Wave w
+    // owns the 16-column blocks w, w+4, ... of the 32 x nb output; its lanes
+    // load Z straight from P, V or the slab in LDS (32 loads in flight per
+    // batch of 128 rows), V_s^T comes from LDS; no workgroup barriers.
     double *mypart = part_up + (size_t)wg * W * nb;
     const int lane = t & 63, wave = t >> 6, li = lane & 15, lk = lane >> 4;
-    for (int cc = 0; cc < nb; cc += 32) {
-      // stage Z(:, cc .. cc+31); global loads issued 8 at a time (one
-      // workgroup per CU: a load per iteration would expose every round trip)
-      for (int base = 0; base < 32 * rpw4; base += 8 * kPThreads) {
-        double z[8];
+    {
+      const int nbk = (nb + 15) / 16, KS = rpw4 / 4;
+      for (int jb = wave; jb < nbk; jb += kPThreads / 64) {
+        const int col = 16 * jb + li;
+        const bool inP = col < nb && col >= cs + ws, inX = col >= cs && col < cs + ws, inV = col < cs;
+        const double *src = inP ? p.P + rbeg + (int64_t)col * p.ldp : (inV ? p.V + rbeg + (int64_t)col * p.ldv : p.P);
+        d4 acc[2][2];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = base + t + u * kPThreads;
-          const int c = idx / rpw4, r = idx % rpw4, col = cc + c;
-          z[u] = 0.0;
-          if (idx < 32 * rpw4 && col < nb && r < nrow) {
-            if (col >= cs + ws) z[u] = p.P[(rbeg + r) + (int64_t)col * p.ldp];
-            else if (col >= cs) z[u] = X[(col - cs) * ldx + r];
-            else z[u] = p.V[(rbeg + r) + (int64_t)col * p.ldv];
+        for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < KS; kb += 32) {
+          double bz[32];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) {
+            const int r = 4 * (kb + u) + lk;
+            double z = 0.0;
+            if (kb + u < KS && r < nrow) z = inX ? X[(col - cs) * ldx + r] : ((inP || inV) ? src[r] : 0.0);
+            bz[u] = z;
+          }
+#pragma unroll
+          for (int u = 0; u < 32; ++u) {
+            if (kb + u < KS) {
+              const int r = 4 * (kb + u) + lk;
+              acc[0][u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[li * ldx + r], bz[u], acc[0][u & 1], 0, 0, 0);
+              acc[1][u & 1] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(X[(16 + li) * ldx + r], bz[u], acc[1][u & 1], 0, 0, 0);
+            }
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = base + t + u * kPThreads;
-          if (idx < 32 * rpw4) Zc[(idx / rpw4) * ldz + idx % rpw4] = z[u];
-        }
-      }
-      __syncthreads();
-      {
-        const int ib = wave & 1, jb = wave >> 1;
-        const double *xa = X + (16 * ib + li) * ldx + lk;
-        const double *zb = Zc + (16 * jb + li) * ldz + lk;
-        d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        int k0 = 0;
-        for (; k0 + 8 <= rpw4; k0 += 8) {
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0], zb[k0], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0 + 4], zb[k0 + 4], acc1, 0, 0, 0);
-        }
-        if (k0 < rpw4) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0], zb[k0], acc0, 0, 0, 0);
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = 16 * ib + 4 * q + lk, col = cc + 16 * jb + li;
-          if (i < ws && col < nb) mypart[i * nb + col] = acc0[q] + acc1[q];
-        }
+          for (int q = 0; q < 4; ++q) {
+            const int i = 16 * a + 4 * q + lk;
+            if (i < ws && col < nb) mypart[i * nb + col] = acc[a][0][q] + acc[a][1][q];
+          }
       }
-      __syncthreads();
     }
     ok = grid_sync(gb, gen, true);
     if (!ok) break;
@@ -482,8 +478,8 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 }
 
 size_t panel_lds_doubles(int rpw, int nb) {
-  const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded strides
-  return (size_t)W * ld + (size_t)W * ld + (size_t)W * nb + W * W + 640 + W;
+  const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded stride
+  return (size_t)W * ld + (size_t)W * nb + W * W + 640 + W;
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
