@@ -20,6 +20,8 @@ struct rqrcp_timing_rec {
 
 struct rqrcp_ctx {
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;          // library-owned, default priority: work that overlaps the main stream
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
@@ -247,17 +249,19 @@ struct ScopedTimer {
   int kclass;
   double flops, bytes;
   hipEvent_t start = nullptr;
-  ScopedTimer(rqrcp_handle_t hh, int kc, double f, double b) : h(hh), kclass(kc), flops(f), bytes(b) {
+  hipStream_t stream;
+  ScopedTimer(rqrcp_handle_t hh, int kc, double f, double b, hipStream_t st = nullptr)
+      : h(hh), kclass(kc), flops(f), bytes(b), stream(st ? st : hh->stream) {
     if (h->timing) {
       start = take_event(h);
-      if (start) (void)hipEventRecord(start, h->stream);
+      if (start) (void)hipEventRecord(start, stream);
     }
   }
   ~ScopedTimer() {
     if (!start) return;
     hipEvent_t stop = take_event(h);
     if (!stop) return;
-    (void)hipEventRecord(stop, h->stream);
+    (void)hipEventRecord(stop, stream);
     h->recs.push_back({kclass, start, stop, flops, bytes});
   }
 };
@@ -317,6 +321,15 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   if (e != hipSuccess) return fail_hip(nullptr, e, "hipDeviceGetAttribute(WallClockRate)");
   rqrcp_ctx *c = new rqrcp_ctx();
   c->stream = static_cast<hipStream_t>(hip_stream);
+  e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    delete c;
+    return fail_hip(nullptr, e, "side stream / events");
+  }
   c->device = dev;
   c->limit_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 2000ull;
   *h = c;
@@ -331,7 +344,11 @@ rqrcp_status_t rqrcp_set_stream(rqrcp_handle_t h, void *hip_stream) {
 
 rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
   if (!h) return RQRCP_OK;
+  if (h->side) (void)hipStreamSynchronize(h->side);
   for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  if (h->side) (void)hipStreamDestroy(h->side);
   delete h;
   return RQRCP_OK;
 }
@@ -580,23 +597,22 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       if constexpr (F32) CHK(launch_copy_f64_f32(s, Pw, mi, X, lda, mi, bi), "panel to FP32");
     }
     double *Ti = Tout + (size_t)i * b * b;
-    {
+    if (ni <= bi) {
       ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
       CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
-    }
-    if (ni > bi) {
-      // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1)
+    } else {
+      // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1).  W = V^T C
+      // does not need T: T is formed on the side stream meanwhile (one
+      // workgroup per block row would leave most of the chip idle).
       T *C = X + bi * lda;
       const double nc = (double)(ni - bi);
+      CHK(hipEventRecord(h->fork_ev, s), "fork event");
+      CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
       {
-        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
-        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
-        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
-        if constexpr (F32) {
-          CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
-          CHK(launch_copy_f64_f32(s, VT, b, VT32, b, bi, mi), "V^T to FP32");
-        }
+        ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
+        CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
       }
+      CHK(hipEventRecord(h->join_ev, h->side), "join event");
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
@@ -604,9 +620,17 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           GemmF64 gw{false, false, bi, ni - bi, mi, VT, b, C, lda, Wb, bi, 1.0, 0.0};
           CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
         } else {
+          CHK(launch_copy_f64_f32(s, VT, b, VT32, b, bi, mi), "V^T to FP32");
           GemmF32 gw{false, false, bi, ni - bi, mi, VT32, b, C, lda, W32, bi, 1.f, 0.f};
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
+      }
+      CHK(hipStreamWaitEvent(s, h->join_ev, 0), "join T");
+      {
+        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
+        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
+        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
+        if constexpr (F32) CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
       }
       {
         ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,

@@ -495,7 +495,8 @@ size_t panel_lds_doubles(int rpw, int nb) {
 // whole block row (zeros left of the diagonal block) to T.
 // S(q, j) is read only for q < (J+1)*W, the part the panel kernel fills.
 constexpr int kTThreads = 256;
-constexpr int kTBlk = W * W + 2;   // staged diagonal block of S, padded against bank conflicts
+constexpr int kTLd = W + 1;        // row stride of staged blocks of S (odd: no bank conflicts)
+constexpr int kTBlk = W * kTLd;    // one staged W x W block of S
 
 __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *__restrict__ tau,
                                                          const double *__restrict__ S, double *__restrict__ T,
@@ -516,9 +517,21 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
   for (int J0 = I; J0 < nslab; J0 += g1) {
     const int ng = min(g1, nslab - J0);
     __syncthreads();
-    for (int idx = t; idx < ng * W * W; idx += kTThreads) {
-      const int g = idx / (W * W), u = (idx / W) % W, jj = idx % W, cJ = (J0 + g) * W;
-      St[(size_t)g * kTBlk + u * W + jj] = Sg(cJ + u, cJ + jj);
+    // S is column-major: consecutive threads read consecutive rows u (coalesced), 8 loads in flight
+    for (int base = 0; base < ng * W * W; base += 8 * kTThreads) {
+      double x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = base + t + q * kTThreads;
+        const int g = idx / (W * W), jj = (idx / W) % W, u = idx % W, cJ = (J0 + g) * W;
+        x[q] = idx < ng * W * W ? Sg(cJ + u, cJ + jj) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = base + t + q * kTThreads;
+        const int g = idx / (W * W), jj = (idx / W) % W, u = idx % W;
+        if (idx < ng * W * W) St[(size_t)g * kTBlk + u * kTLd + jj] = x[q];
+      }
     }
     __syncthreads();
     for (int task = t; task < ng * W; task += kTThreads) {
@@ -529,7 +542,7 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
         const double tj = taul[cJ + jj];
         double acc = 0.0;
 #pragma unroll 4
-        for (int u = r; u < jj; ++u) acc += d[u] * sj[u * W + jj];
+        for (int u = r; u < jj; ++u) acc += d[u] * sj[u * kTLd + jj];
         d[jj] = jj < r ? 0.0 : (jj == r ? tj : -tj * acc);
       }
     }
@@ -543,15 +556,27 @@ __global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *_
     for (int K0 = I; K0 < J; K0 += g2) {
       const int nk = min(g2, J - K0);
       __syncthreads();
-      for (int idx = t; idx < nk * W * W; idx += kTThreads) {
-        const int q = idx / W, cc = idx % W;      // q: row within the chunk
-        St[(size_t)q * W + cc] = Sg(K0 * W + q, cJ + cc);
+      // rows q of the chunk fastest (coalesced reads of S), 8 loads in flight
+      for (int base = 0; base < nk * W * W; base += 8 * kTThreads) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + t + u * kTThreads;
+          const int cc = idx / (nk * W), q = idx % (nk * W);
+          x[u] = idx < nk * W * W ? Sg(K0 * W + q, cJ + cc) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + t + u * kTThreads;
+          const int cc = idx / (nk * W), q = idx % (nk * W);
+          if (idx < nk * W * W) St[(size_t)q * kTLd + cc] = x[u];
+        }
       }
       __syncthreads();
       const double *r0 = R + (size_t)(4 * rq) * ldr + (K0 * W - cI);
 #pragma unroll 8
       for (int q = 0; q < nk * W; ++q) {
-        const double sv = St[(size_t)q * W + c];
+        const double sv = St[(size_t)q * kTLd + c];
         a0 += r0[q] * sv;
         a1 += r0[ldr + q] * sv;
         a2 += r0[2 * ldr + q] * sv;
@@ -627,11 +652,11 @@ hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S
   const size_t fixed = (size_t)W * (nslab * W + 1) + W * (W + 1) + (size_t)nslab * W;   // the kernel's layout
   if (fixed + kTBlk > kLdsDoubles) return hipErrorInvalidValue;
   const size_t room = kLdsDoubles - fixed;
-  int g1 = (int)(room / kTBlk), g2 = (int)(room / (W * W));
+  int g1 = (int)(room / kTBlk), g2 = (int)(room / kTBlk);
   g1 = g1 > kTThreads / W ? kTThreads / W : g1;
   g1 = g1 > nslab ? nslab : g1;
   g2 = g2 > nslab ? nslab : g2;
-  const size_t stage = (size_t)(g1 * kTBlk > g2 * W * W ? g1 * kTBlk : g2 * W * W);
+  const size_t stage = (size_t)(g1 > g2 ? g1 : g2) * kTBlk;
   const size_t bytes = (fixed + stage) * sizeof(double);
   static bool attr_done = false;
   if (!attr_done) {
