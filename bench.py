@@ -43,7 +43,7 @@ def parse():
     return ap.parse_args()
 
 
-GEMM_SOURCES = ("paper_1505_08115_amd/csrc/gemm.hip", "paper_1505_08115_amd/csrc/common.h")
+GEMM_SOURCES = ("paper_1505_08115_amd/csrc/gemm.hip",)   # the file that defines the GEMM kernels
 PMC_SUMMARY = "profiles/update_gemm_H1_pmc.txt"
 
 
