@@ -19,6 +19,8 @@
 //     reduce-scattered (two barriers); they give the Gram rows needed for T
 //     and W = V_s^T A_rest, which updates the rest of the panel as
 //     A_rest <- A_rest - V_s (T_s^T W).
+#include <type_traits>
+
 #include "common.h"
 
 namespace rq {
@@ -103,11 +105,8 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
             for (int r = r0 + sub; r < nrow; r += 8) g0 += X[jj * ldx + r] * X[c * ldx + r];
           }
         }
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-          g0 += __shfl_xor(g0, off, 64);
-          g1 += __shfl_xor(g1, off, 64);
-        }
+        g0 = group8_sum(g0);
+        g1 = group8_sum(g1);
         if (sub == 0 && c < ws) {
           const double h0 = (j >= rbeg && j < rbeg + nrow) ? X[c * ldx + (int)(j - rbeg)] : 0.0;
           const double h1 = (j + 1 >= rbeg && j + 1 < rbeg + nrow) ? X[c * ldx + (int)(j + 1 - rbeg)] : 0.0;
@@ -122,36 +121,42 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int e = t + 64 * q;
-            if (e % W < E && (q == 0 || pair)) part_cs[((size_t)buf * nwg + wg) * 4 * W + e] = sc[e];
+            if (e % W < E && (q == 0 || pair)) st_agent(part_cs + ((size_t)buf * nwg + wg) * 4 * W + e, sc[e]);
           }
         }
       }
-      ok = grid_sync(gb, gen);
+      // exchange mode: the partials are written and read with agent-scope atomics
+      ok = grid_sync(gb, gen, false, true);
       if (!ok) break;
-      // fixed-order reduction: 4 groups of workgroups, then the groups in order;
-      // thread (grp, e) sums entries e and 64 + e
+      // fixed-order reduction of the sums g0, g1: 4 groups of workgroups, then
+      // the groups in order; thread (grp, e) sums entry e of [g0 | g1].  The
+      // row entries h0, h1 are read once, from the workgroups owning rows j
+      // and j + 1 (every other workgroup's are zero).
       {
         const int e = t & 63, grp = t >> 6;
-        const bool v0 = e % W < E, v1 = pair && e % W < E;
-        double acc0 = 0.0, acc1 = 0.0;
-        // loads issued 32 at a time (one round trip at 64 workgroups), summed in workgroup order
+        const int ent = e < W ? e : 2 * W + (e - W);             // g0_e or g1_(e-W)
+        const bool live = e < W ? e < E : (pair && e - W < E);
+        double acc = 0.0;
+        // 16 loads in flight per thread (one round trip at 64 workgroups), summed in workgroup order
         for (int w0 = grp; w0 < nwg; w0 += 64) {
-          double x0[16], x1[16];
+          double x[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int w2 = w0 + 4 * u;
             const double *src = part_cs + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 4 * W;
-            x0[u] = (v0 && w2 < nwg) ? src[e] : 0.0;
-            x1[u] = (v1 && w2 < nwg) ? src[64 + e] : 0.0;
+            x[u] = (live && w2 < nwg) ? ld_agent(src + ent) : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            acc0 += x0[u];
-            acc1 += x1[u];
-          }
+          for (int u = 0; u < 16; ++u) acc += x[u];
         }
-        sc[grp * 128 + e] = acc0;
-        sc[grp * 128 + 64 + e] = acc1;
+        double h = 0.0;
+        if (grp == 0 && live) {
+          const int64_t row = e < W ? j : j + 1;
+          const int owner = (int)(row / rpw);
+          h = ld_agent(part_cs + ((size_t)buf * nwg + owner) * 4 * W + ent + W);
+        }
+        sc[grp * 128 + ent] = acc;
+        sc[grp * 128 + ent + W] = h;
         __syncthreads();
         if (t < 128) sc[t] = ((sc[t] + sc[128 + t]) + sc[256 + t]) + sc[384 + t];
         __syncthreads();
@@ -274,48 +279,58 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     // matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j]
     // from lane j + 16k, D[i][j] in lane j + 16 (i%4), register i/4).  Wave w
     // owns the 16-column blocks w, w+4, ... of the 32 x nb output; its lanes
-    // load Z straight from P, V or the slab in LDS (32 loads in flight per
-    // batch of 128 rows), V_s^T comes from LDS; no workgroup barriers.
+    // load Z straight from V (every column left of A_rest, the slab's
+    // explicit V written above included) or P (A_rest), up to 32 loads in
+    // flight; V_s^T comes from LDS.  Batches have a fixed size (32, 16, ...,
+    // 1 steps of K), so the loads and MFMAs of a batch are straight-line code.
     double *mypart = part_up + (size_t)wg * W * nb;
     const int lane = t & 63, wave = t >> 6, li = lane & 15, lk = lane >> 4;
     {
-      const int nbk = (nb + 15) / 16, KS = rpw4 / 4;
+      const int nbk = (nb + 15) / 16, KS = rpw4 / 4, nr1 = max(nrow - 1, 0);
       for (int jb = wave; jb < nbk; jb += kPThreads / 64) {
         const int col = 16 * jb + li;
-        const bool inP = col < nb && col >= cs + ws, inX = col >= cs && col < cs + ws, inV = col < cs;
-        const double *src = inP ? p.P + rbeg + (int64_t)col * p.ldp : (inV ? p.V + rbeg + (int64_t)col * p.ldv : p.P);
+        const bool have = col < nb && nrow > 0;
+        const double *src = !have ? p.P
+                                  : (col < cs + ws ? p.V + rbeg + (int64_t)col * p.ldv
+                                                   : p.P + rbeg + (int64_t)col * p.ldp);
         d4 acc[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < KS; kb += 32) {
-          double bz[32];
+        int kb = 0;
+        // every batch but the last has an even size, so step kb + u goes to chain u & 1
+        auto batch = [&](auto nbc) {
+          constexpr int NB = decltype(nbc)::value;
+          double bz[NB];
 #pragma unroll
-          for (int u = 0; u < 32; ++u) {
+          for (int u = 0; u < NB; ++u) {
             const int r = 4 * (kb + u) + lk;
-            double z = 0.0;
-            if (kb + u < KS && r < nrow) z = inX ? X[(col - cs) * ldx + r] : ((inP || inV) ? src[r] : 0.0);
-            bz[u] = z;
+            const double z = src[have ? min(r, nr1) : 0];
+            bz[u] = (have && r < nrow) ? z : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 32; ++u) {
-            if (kb + u < KS) {
-              const int r = 4 * (kb + u) + lk;
-              acc[0][u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[li * ldx + r], bz[u], acc[0][u & 1], 0, 0, 0);
-              acc[1][u & 1] =
-                  __builtin_amdgcn_mfma_f64_16x16x4f64(X[(16 + li) * ldx + r], bz[u], acc[1][u & 1], 0, 0, 0);
-            }
+          for (int u = 0; u < NB; ++u) {
+            const int r = 4 * (kb + u) + lk;
+            acc[0][u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[li * ldx + r], bz[u], acc[0][u & 1], 0, 0, 0);
+            acc[1][u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[(16 + li) * ldx + r], bz[u], acc[1][u & 1], 0, 0, 0);
           }
-        }
+          kb += NB;
+        };
+        while (KS - kb >= 32) batch(std::integral_constant<int, 32>{});
+        if (KS - kb >= 16) batch(std::integral_constant<int, 16>{});
+        if (KS - kb >= 8) batch(std::integral_constant<int, 8>{});
+        if (KS - kb >= 4) batch(std::integral_constant<int, 4>{});
+        if (KS - kb >= 2) batch(std::integral_constant<int, 2>{});
+        if (KS - kb >= 1) batch(std::integral_constant<int, 1>{});
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int i = 16 * a + 4 * q + lk;
-            if (i < ws && col < nb) mypart[i * nb + col] = acc[a][0][q] + acc[a][1][q];
+            if (i < ws && col < nb) st_agent(mypart + i * nb + col, acc[a][0][q] + acc[a][1][q]);
           }
       }
     }
-    ok = grid_sync(gb, gen, true);
+    ok = grid_sync(gb, gen, true, true);   // exchange mode, every wave stored partials
     if (!ok) break;
     {
       // reduce-scatter: this workgroup sums elements [beg, end) over all
@@ -336,7 +351,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           for (int wb = w0; wb < w1; wb += 8) {
             double x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = wb + u < w1 ? part_up[(size_t)(wb + u) * W * nb + e] : 0.0;
+            for (int u = 0; u < 8; ++u) x[u] = wb + u < w1 ? ld_agent(part_up + (size_t)(wb + u) * W * nb + e) : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc += x[u];
           }
@@ -345,12 +360,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         if (g == 0 && e < end) {
           double tot = sc[t];
           for (int h = 1; h < G; ++h) tot += sc[t + h];
-          p.red[e] = tot;
+          st_agent(p.red + e, tot);
         }
         __syncthreads();
       }
     }
-    ok = grid_sync(gb, gen, true);
+    ok = grid_sync(gb, gen, true, true);
     if (!ok) break;
     // the reduced rows V_s^T [V_0 .. V_s | A_rest] -> LDS (row tt at Wp + tt*nb), 8 loads in flight
     for (int base = 0; base < ws * nb; base += 8 * kPThreads) {
@@ -358,7 +373,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = base + t + u * kPThreads;
-        x[u] = idx < ws * nb ? p.red[idx] : 0.0;
+        x[u] = idx < ws * nb ? ld_agent(p.red + idx) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -429,24 +444,34 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       // (D[i][j] = sum_tt W(tt, c0 + i) X(r0 + j, tt)) so that each lane
       // holds consecutive rows of one column of P: 16 x 16 blocks dealt to waves
       {
-        // four blocks per pass: their 16 loads of P are issued before the MFMAs
+        // four blocks per pass: their 16 loads of P are issued before the MFMAs,
+        // and the next pass's loads before this pass's MFMAs (two buffers)
         const int rb = (nrow + 15) / 16, cb = (rest + 15) / 16, nblk = rb * cb;
         constexpr int NW = kPThreads / 64, GB = 4;
-        for (int b0 = wave * GB; b0 < nblk; b0 += NW * GB) {
-          double pv[GB][4];
-          d4 acc[GB];
+        double pv[2][GB][4];
+        auto load = [&](auto bufc, int b0) {
+          constexpr int B = decltype(bufc)::value;
 #pragma unroll
           for (int u = 0; u < GB; ++u) {
             const int blk = b0 + u;
             const int r = 16 * (blk % rb) + li, c0 = 16 * (blk / rb);
-            acc[u] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int c = c0 + 4 * q + lk;
-              pv[u][q] = (blk < nblk && r < nrow && c < rest) ? p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] : 0.0;
+              pv[B][u][q] =
+                  (blk < nblk && r < nrow && c < rest) ? p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] : 0.0;
             }
           }
-          for (int k0 = 0; k0 < ws; k0 += 4) {
+        };
+        auto update = [&](auto bufc, int b0) {
+          constexpr int B = decltype(bufc)::value;
+          d4 acc[GB];
+#pragma unroll
+          for (int u = 0; u < GB; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+          // all W steps (rows tt >= ws of W read as zero and columns tt >= ws of
+          // X T_s^T are zero): straight-line MFMAs, accumulators stay put
+#pragma unroll
+          for (int k0 = 0; k0 < W; k0 += 4) {
             const int tt = k0 + lk;
 #pragma unroll
             for (int u = 0; u < GB; ++u) {
@@ -466,9 +491,21 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
             for (int q = 0; q < 4; ++q) {
               const int c = c0 + 4 * q + lk;
               if (blk < nblk && r < nrow && c < rest)
-                p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] = pv[u][q] - acc[u][q];
+                p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] = pv[B][u][q] - acc[u][q];
             }
           }
+        };
+        constexpr auto b0c = std::integral_constant<int, 0>{};
+        constexpr auto b1c = std::integral_constant<int, 1>{};
+        constexpr int step = NW * GB;
+        const int first = wave * GB;
+        if (first < nblk) load(b0c, first);
+        for (int b0 = first; b0 < nblk; b0 += 2 * step) {
+          if (b0 + step < nblk) load(b1c, b0 + step);
+          update(b0c, b0);
+          if (b0 + step >= nblk) break;
+          if (b0 + 2 * step < nblk) load(b0c, b0 + 2 * step);
+          update(b1c, b0 + step);
         }
       }
     }

@@ -47,16 +47,45 @@ __device__ void flag_nonfinite(int32_t *info, int block_index) {
   atomicCAS(&info[1], 0, block_index + 1);
 }
 
-// Arg-max over the lanes of one wave of (val, pos, idx); ties go to the lower
-// pos.  Every lane returns the winner.
+// One arg-max exchange of (val, pos, idx) with the lane that CTRL selects;
+// ties go to the lower pos.  Both lanes of a pair end with the same triple.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &p, int &i) {
+  const double v2 = dpp_mov<CTRL>(v);
+  const int p2 = dpp_mov<CTRL>(p), i2 = dpp_mov<CTRL>(i);
+  if (better(v2, p2, v, p)) { v = v2; p = p2; i = i2; }
+}
+// The same across lanes i and i ^ SPAN (16 or 32): both lanes see the pair
+// in the same order and pick the same member.
+template <int SPAN>
+__device__ __forceinline__ void argmax_span(double &v, int &p, int &i) {
+  double vl, vh;
+  int pl, ph, il, ih;
+  lane_pair<SPAN>(v, vl, vh);
+  lane_pair<SPAN>(p, pl, ph);
+  lane_pair<SPAN>(i, il, ih);
+  const bool up = better(vh, ph, vl, pl);
+  v = up ? vh : vl;
+  p = up ? ph : pl;
+  i = up ? ih : il;
+}
+// Arg-max over aligned groups of 8 lanes (every lane of a group gets the winner).
+__device__ __forceinline__ void group8_argmax(double &v, int &p, int &i) {
+  argmax_dpp<kDppXor1>(v, p, i);
+  argmax_dpp<kDppXor2>(v, p, i);
+  argmax_dpp<kDppHalfMirror>(v, p, i);
+}
+// Arg-max over the wave, given that the lanes of each group of 8 agree.
+__device__ __forceinline__ void groups_argmax(double &v, int &p, int &i) {
+  argmax_dpp<kDppMirror>(v, p, i);
+  argmax_span<16>(v, p, i);
+  argmax_span<32>(v, p, i);
+}
+// Arg-max over the lanes of one wave; every lane returns the winner.  Call
+// with all 64 lanes active.
 __device__ __forceinline__ void wave_argmax(double &v, int &p, int &i) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double v2 = __shfl_xor(v, off, 64);
-    const int p2 = __shfl_xor(p, off, 64);
-    const int i2 = __shfl_xor(i, off, 64);
-    if (better(v2, p2, v, p)) { v = v2; p = p2; i = i2; }
-  }
+  group8_argmax(v, p, i);
+  groups_argmax(v, p, i);
 }
 
 // Squared norm as a pivot key: non-finite values never win (and are flagged).
@@ -248,28 +277,11 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
   for (int r = t; r < KP; r += kQThreads) v[r] = 0.0;
   int pos = col, act = valid ? 1 : 0;
 
-  // group sum over the 8 lanes of a column
-  auto gsum = [](double x) {
-    x += __shfl_xor(x, 1, 64);
-    x += __shfl_xor(x, 2, 64);
-    x += __shfl_xor(x, 4, 64);
-    return x;
-  };
-  // wave arg-max over the 8 columns of a wave (lanes of a group agree)
-  auto wmax = [](double &bv, int &bp, int &bi) {
-#pragma unroll
-    for (int off = 8; off <= 32; off <<= 1) {
-      const double v2 = __shfl_xor(bv, off, 64);
-      const int p2 = __shfl_xor(bp, off, 64);
-      const int i2 = __shfl_xor(bi, off, 64);
-      if (better(v2, p2, bv, bp)) { bv = v2; bp = p2; bi = i2; }
-    }
-  };
   // publish this wave's best column to LDS (all rows; readers use rows >= j)
   auto wave_best = [&](double key) {
     double bv = act ? key : -1.0;
     int bp = act ? pos : INT_MAX, bi = act ? col : -1;
-    wmax(bv, bp, bi);
+    groups_argmax(bv, bp, bi);   // the lanes of a column group agree
     if (bi >= 0 && col == bi) {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) cb[wave][sub + kRLanes * i] = y[i];
@@ -281,7 +293,7 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
     double s2 = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) s2 += y[i] * y[i];
-    s2 = gsum(s2);
+    s2 = group8_sum(s2);
     s2 = key_of(s2, q.info, q.block_index, valid ? sub : 1);
     wave_best(s2);
   }
@@ -296,19 +308,21 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
       double bv = lane < kQWaves ? wbv[lane] : -1.0;
       int bp = lane < kQWaves ? wbp[lane] : INT_MAX;
       int bw = lane < kQWaves ? lane : -1;
-      wave_argmax(bv, bp, bw);
+      group8_argmax(bv, bp, bw);   // lanes 0..7 hold the 8 wave bests
+      bw = lane0(bw);
       double *myrec = q.rec + ((size_t)buf * nwg + wg) * 4;
       double *mycand = q.cand + ((size_t)buf * nwg + wg) * k;
       const int bi = bw >= 0 ? wbi[bw] : -1;
       if (bi >= 0)
-        for (int r = j + lane; r < k; r += 64) mycand[r] = cb[bw][r];
+        for (int r = j + lane; r < k; r += 64) st_agent(mycand + r, cb[bw][r]);
       if (lane == 0) {
-        myrec[0] = bv;
-        myrec[1] = (double)bp;
-        myrec[2] = (double)bi;
+        st_agent(myrec, bv);
+        st_agent(myrec + 1, (double)bp);
+        st_agent(myrec + 2, (double)bi);
       }
     }
-    ok = grid_sync(gb, gen);
+    // exchange mode: records and columns are written and read with agent-scope atomics
+    ok = grid_sync(gb, gen, false, true);
     if (!ok) break;
     // wave 0: global winner, its column and the reflector (Section 3.1)
     if (wave == 0) {
@@ -319,7 +333,7 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
       for (int u = 0; u < 4; ++u) {           // nwg <= 256: all records in one round of loads
         const int w2 = lane + 64 * u;
         const double *rr = q.rec + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 4;
-        rv[u] = rr[0]; rp[u] = rr[1]; rc[u] = rr[2];
+        rv[u] = ld_agent(rr); rp[u] = ld_agent(rr + 1); rc[u] = ld_agent(rr + 2);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {           // gi packs (workgroup << 16) | column
@@ -329,6 +343,8 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
         }
       }
       wave_argmax(gv, gp, gi);
+      gp = lane0(gp);
+      gi = lane0(gi);
       const int gcol = gi & 0xFFFF;
       gi = gi < 0 ? -1 : gi >> 16;
       if (gi < 0) {
@@ -339,14 +355,14 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
 #pragma unroll
         for (int u = 0; u < kRMaxRows / 64; ++u) {
           const int r = j + lane + 64 * u;
-          xs[u] = r < k ? wc[r] : 0.0;
+          xs[u] = r < k ? ld_agent(wc + r) : 0.0;
         }
         double s2 = 0.0;
 #pragma unroll
         for (int u = 0; u < kRMaxRows / 64; ++u) s2 += xs[u] * xs[u];
         s2 = wave_sum(s2);
         double tau = 0.0, scale = 1.0;
-        const double a = __shfl(xs[0], 0, 64);   // row j
+        const double a = lane0(xs[0]);   // row j
         if (j < k - 1 && s2 != 0.0) {
           const double beta = (a >= 0.0 ? -1.0 : 1.0) * sqrt(s2);
           tau = (beta - a) / beta;
@@ -380,7 +396,7 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
       pos = wpos;
     }
     // straight-line code (no per-row branches): v is zero on rows < j and
-    // past k, the norm takes rows > j by a select
+    // past k, and rows < j of y were zeroed at earlier steps
     if (tau != 0.0) {
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
@@ -388,7 +404,7 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
         d0 += v[sub + kRLanes * i] * y[i];
         if (i + 1 < RPL) d1 += v[sub + kRLanes * (i + 1)] * y[i + 1];
       }
-      const double d = gsum(d0 + d1);
+      const double d = group8_sum(d0 + d1);
       const double f = act ? tau * d : 0.0;
       // up to 40 rows per lane v stays in registers between the two loops;
       // beyond that it would spill, so the update re-reads it from LDS
@@ -396,17 +412,22 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
 #pragma unroll
       for (int i = 0; i < RPL; ++i) y[i] -= f * v[sub + kRLanes * i];
     }
+    // row j now holds an entry of R, which no later decision uses: zero it,
+    // so that all rows <= j of y are zero and the norm over rows > j is a
+    // plain sum (adding the zeros changes no bit of it)
+    {
+      const int ib = j / kRLanes, sj = j % kRLanes;   // wave-uniform
+#pragma unroll
+      for (int i = 0; i < RPL; ++i)
+        if (i == ib) y[i] = sub == sj ? 0.0 : y[i];
+    }
     double s20 = 0.0, s21 = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; i += 2) {
-      const double a = (sub + kRLanes * i > j) ? y[i] : 0.0;
-      s20 += a * a;
-      if (i + 1 < RPL) {
-        const double c = (sub + kRLanes * (i + 1) > j) ? y[i + 1] : 0.0;
-        s21 += c * c;
-      }
+      s20 += y[i] * y[i];
+      if (i + 1 < RPL) s21 += y[i + 1] * y[i + 1];
     }
-    double s2 = gsum(s20 + s21);
+    double s2 = group8_sum(s20 + s21);
     s2 = key_of(s2, q.info, q.block_index, act ? sub : 1);
     wave_best(s2);
   }
@@ -460,7 +481,7 @@ size_t lds_doubles(int k, int cpw) {
 
 static int rpl_for(int k) {
   const int r = (k + kRLanes - 1) / kRLanes;
-  return r <= 4 ? 4 : ((r + 7) / 8) * 8;
+  return ((r + 3) / 4) * 4;   // rows per lane rounded up to a multiple of 4
 }
 
 int qrcp_small_config(int k, int ncols, int *cpw) {
@@ -505,11 +526,17 @@ hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
     switch (rpl_for(q.k)) {
       case 4: return launch_reg<4>(s, nwg, q);
       case 8: return launch_reg<8>(s, nwg, q);
+      case 12: return launch_reg<12>(s, nwg, q);
       case 16: return launch_reg<16>(s, nwg, q);
+      case 20: return launch_reg<20>(s, nwg, q);
       case 24: return launch_reg<24>(s, nwg, q);
+      case 28: return launch_reg<28>(s, nwg, q);
       case 32: return launch_reg<32>(s, nwg, q);
+      case 36: return launch_reg<36>(s, nwg, q);
       case 40: return launch_reg<40>(s, nwg, q);
+      case 44: return launch_reg<44>(s, nwg, q);
       case 48: return launch_reg<48>(s, nwg, q);
+      case 52: return launch_reg<52>(s, nwg, q);
       default: return launch_reg<56>(s, nwg, q);
     }
   }
