@@ -289,10 +289,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       const int nbk = (nb + 15) / 16, KS = rpw4 / 4, nr1 = max(nrow - 1, 0);
       for (int jb = wave; jb < nbk; jb += kPThreads / 64) {
         const int col = 16 * jb + li;
-        const bool have = col < nb && nrow > 0;
-        const double *src = !have ? p.P
-                                  : (col < cs + ws ? p.V + rbeg + (int64_t)col * p.ldv
-                                                   : p.P + rbeg + (int64_t)col * p.ldp);
+        // columns past nb load column nb - 1 (their outputs are never stored);
+        // a workgroup without rows loads row 0 of P (its X is all zero)
+        const int cl = min(col, nb - 1);
+        const double *src = nrow == 0 ? p.P
+                                      : (cl < cs + ws ? p.V + rbeg + (int64_t)cl * p.ldv
+                                                      : p.P + rbeg + (int64_t)cl * p.ldp);
         d4 acc[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][0] = acc[a][1] = d4{0.0, 0.0, 0.0, 0.0};
@@ -303,10 +305,10 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           double bz[NB];
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
-            const int r = 4 * (kb + u) + lk;
-            const double z = src[have ? min(r, nr1) : 0];
-            bz[u] = (have && r < nrow) ? z : 0.0;
+            // rows past nrow load row nrow - 1: their V_s^T rows in X are zero
+            bz[u] = src[min(4 * (kb + u) + lk, nr1)];
           }
+          __builtin_amdgcn_sched_barrier(0);   // all loads of the batch issue before its MFMAs
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
             const int r = 4 * (kb + u) + lk;
@@ -390,26 +392,34 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         p.S[q + (int64_t)(cs + tt) * nb] = Wp[tt * nb + q];
       }
     // T_s by the recurrence T(r, tt) = -tau_tt sum_{r<=u<tt} T(r, u) v_u^T v_tt,
-    // which involves only row r: lane r of wave 0 keeps its row in registers
-    // (entries left of the diagonal are zero, so the sums can run over u < tt)
-    if (t < W) {
-      const int r = t;
-      double tr[W];
+    // which involves only row r.  Eight lanes share a row (all 256 threads:
+    // 32 rows x 8): lane `part` keeps T(r, u) for u = part + 8i in registers
+    // and sums those terms, a group sum over the 8 lanes completes each entry,
+    // and the lane owning column tt keeps it.  Entries not yet formed are zero,
+    // so every sum may run over all u; the loads of v_u^T v_tt do not depend
+    // on T and run ahead of the 32-step chain.
+    {
+      const int r = t >> 3, part = t & 7;
+      double tr[W / 8];
+#pragma unroll
+      for (int i = 0; i < W / 8; ++i) tr[i] = 0.0;
 #pragma unroll
       for (int tt = 0; tt < W; ++tt) {
-        double a0 = 0.0, a1 = 0.0;
+        double a = 0.0;
 #pragma unroll
-        for (int u = 0; u < tt; u += 2) {
-          a0 += tr[u] * Wp[u * nb + cs + tt];
-          if (u + 1 < tt) a1 += tr[u + 1] * Wp[(u + 1) * nb + cs + tt];
+        for (int i = 0; i < W / 8; ++i) {
+          const int u = part + 8 * i;
+          const double g = Wp[u * nb + cs + tt];
+          a += u < tt ? tr[i] * g : 0.0;
         }
+        a = group8_sum(a);
         const double ta = taus[tt];
         const bool live = r < ws && tt < ws && tt >= r;
-        tr[tt] = !live ? 0.0 : (tt == r ? ta : -ta * (a0 + a1));
-        __asm__ volatile("" ::: "memory");   // keep the loads of later steps from piling up in registers
+        const double v = !live ? 0.0 : (tt == r ? ta : -ta * a);
+        if (part == (tt & 7)) tr[tt >> 3] = v;
       }
 #pragma unroll
-      for (int tt = 0; tt < W; ++tt) Ts[r + tt * W] = tr[tt];
+      for (int i = 0; i < W / 8; ++i) Ts[r + (part + 8 * i) * W] = tr[i];
     }
     __syncthreads();
     const int rest = nb - (cs + ws);
@@ -444,13 +454,14 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       // (D[i][j] = sum_tt W(tt, c0 + i) X(r0 + j, tt)) so that each lane
       // holds consecutive rows of one column of P: 16 x 16 blocks dealt to waves
       {
-        // four blocks per pass: their 16 loads of P are issued before the MFMAs,
-        // and the next pass's loads before this pass's MFMAs (two buffers)
+        // eight blocks per pass: their 32 loads of P (unconditional, clamped to
+        // a valid element; values loaded for absent elements are never stored)
+        // are issued before the pass's MFMAs
         const int rb = (nrow + 15) / 16, cb = (rest + 15) / 16, nblk = rb * cb;
-        constexpr int NW = kPThreads / 64, GB = 4;
-        double pv[2][GB][4];
-        auto load = [&](auto bufc, int b0) {
-          constexpr int B = decltype(bufc)::value;
+        constexpr int NW = kPThreads / 64, GB = 8;
+        const int nr1 = nrow - 1;
+        for (int b0 = wave * GB; b0 < nblk; b0 += NW * GB) {
+          double pv[GB][4];
 #pragma unroll
           for (int u = 0; u < GB; ++u) {
             const int blk = b0 + u;
@@ -458,18 +469,15 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int c = c0 + 4 * q + lk;
-              pv[B][u][q] =
-                  (blk < nblk && r < nrow && c < rest) ? p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] : 0.0;
+              pv[u][q] = p.P[(rbeg + min(r, nr1)) + (int64_t)(cs + ws + min(c, rest - 1)) * p.ldp];
             }
           }
-        };
-        auto update = [&](auto bufc, int b0) {
-          constexpr int B = decltype(bufc)::value;
+          __builtin_amdgcn_sched_barrier(0);
           d4 acc[GB];
 #pragma unroll
           for (int u = 0; u < GB; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-          // all W steps (rows tt >= ws of W read as zero and columns tt >= ws of
-          // X T_s^T are zero): straight-line MFMAs, accumulators stay put
+          // all W steps (rows tt >= ws of W are zero, and so are columns tt >= ws
+          // of X T_s^T): straight-line MFMAs whose LDS operands load ahead
 #pragma unroll
           for (int k0 = 0; k0 < W; k0 += 4) {
             const int tt = k0 + lk;
@@ -478,7 +486,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
               const int blk = min(b0 + u, nblk - 1);
               const int r0 = 16 * (blk % rb), c0 = 16 * (blk / rb);
               const int ca = cs + ws + min(c0 + li, rest - 1);
-              const double a = tt < ws ? Wp[tt * nb + ca] : 0.0;
+              const double a = Wp[tt * nb + ca];                         // rows tt >= ws are zero
               const double bv = X[tt * ldx + min(r0 + li, rpw4 - 1)];   // zero for tt >= ws and pad rows
               acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
             }
@@ -491,21 +499,9 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
             for (int q = 0; q < 4; ++q) {
               const int c = c0 + 4 * q + lk;
               if (blk < nblk && r < nrow && c < rest)
-                p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] = pv[B][u][q] - acc[u][q];
+                p.P[(rbeg + r) + (int64_t)(cs + ws + c) * p.ldp] = pv[u][q] - acc[u][q];
             }
           }
-        };
-        constexpr auto b0c = std::integral_constant<int, 0>{};
-        constexpr auto b1c = std::integral_constant<int, 1>{};
-        constexpr int step = NW * GB;
-        const int first = wave * GB;
-        if (first < nblk) load(b0c, first);
-        for (int b0 = first; b0 < nblk; b0 += 2 * step) {
-          if (b0 + step < nblk) load(b1c, b0 + step);
-          update(b0c, b0);
-          if (b0 + step >= nblk) break;
-          if (b0 + 2 * step < nblk) load(b0c, b0 + 2 * step);
-          update(b1c, b0 + step);
         }
       }
     }
