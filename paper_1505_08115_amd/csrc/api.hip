@@ -22,6 +22,13 @@ struct rqrcp_ctx {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;          // library-owned, default priority: work that overlaps the main stream
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // Library-owned non-blocking stream (default priority): the sketch product
+  // of the next block and the trailing update run there, capped at aux_wg
+  // workgroups (half of the CUs), while the persistent panel and pivoted-QR
+  // kernels run on the main stream and find the other half of the CUs free.
+  hipStream_t aux = nullptr;
+  int aux_wg = 0;
+  hipEvent_t ev_moves = nullptr, ev_ypre = nullptr, ev_vt = nullptr, ev_upd = nullptr;
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
@@ -90,6 +97,9 @@ struct FactorPlan {
   size_t G = 0, Y = 0, YT = 0, Vb = 0, VT = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
          piv = 0, dest = 0, moved = 0, mcnt = 0, tmp = 0, jtmp = 0, bars = 0, Acopy = 0, total = 0;
   size_t Y_doubles = 0;
+  // overlapped schedule (FP64 storage, permutation pivots, sampled blocks)
+  bool pipe = false;
+  size_t GVb = 0, gpart_aux = 0;
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -180,6 +190,19 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     }
   }
   if (!P.f32) gpart32 = 0;
+  // the next block's sketch product and this block's trailing update may run
+  // on the auxiliary stream (own split-K room), the correction G V on the main
+  P.pipe = !P.f32 && !P.ortho && !P.fixed;
+  size_t gpaux = 0;
+  if (P.pipe)
+    for (int64_t i = 0; i + 1 < P.nblocks; ++i) {
+      const int64_t r0 = i * P.b, bi = std::min(P.b, P.k - r0), mi = m - r0, ni = n - r0;
+      if (block_is_classical_tail(P, i + 1) || ni <= bi) continue;
+      gpaux = std::max(gpaux, gemm_part_doubles(P.ks, ni - bi, mi - bi));
+      gpaux = std::max(gpaux, gemm_part_doubles(mi, ni - bi, bi));
+      gpart = std::max(gpart, gemm_part_doubles(P.ks, bi, mi - bi));
+      gpart = std::max(gpart, gemm_part_doubles(P.ks, ni - bi, bi));
+    }
   P.Y_doubles = Yd;
   P.nslots = (int)(3 * P.nblocks + 4);
   Bump w;
@@ -206,6 +229,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.jtmp = w.take((size_t)2 * P.b * 4);
   P.bars = w.take((size_t)P.nslots * kSlotWords * 4);
   P.Acopy = w.take(P.fixed ? (size_t)m * n * es : 0);
+  P.GVb = w.take(P.pipe ? (size_t)P.ks * P.b * d : 0);
+  P.gpart_aux = w.take(gpaux * d);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -324,12 +349,21 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+  hipEvent_t *evs[4] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd};
+  for (hipEvent_t *ev : evs)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
+    for (hipEvent_t *ev : evs)
+      if (*ev) (void)hipEventDestroy(*ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     return fail_hip(nullptr, e, "side stream / events");
   }
+  c->aux_wg = prop.multiProcessorCount / 2;
   c->device = dev;
   c->limit_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 2000ull;
   *h = c;
@@ -345,10 +379,14 @@ rqrcp_status_t rqrcp_set_stream(rqrcp_handle_t h, void *hip_stream) {
 rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
   if (!h) return RQRCP_OK;
   if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  for (hipEvent_t e : {h->ev_moves, h->ev_ypre, h->ev_vt, h->ev_upd})
+    if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   return RQRCP_OK;
 }
@@ -449,7 +487,9 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   float *G32 = at<float>(work, P.G32), *Y32 = at<float>(work, P.Y32);
   float *VS32 = at<float>(work, P.VS32), *TS32 = at<float>(work, P.TS32);
   void *Gb = at<void>(work, P.Gb);
+  double *GVb = at<double>(work, P.GVb), *gpart_aux = at<double>(work, P.gpart_aux);
   int32_t *info = o->info;
+  hipStream_t aux = P.pipe ? h->aux : nullptr;
 
   std::vector<size_t> vs_off(P.nblocks, 0);
   size_t vs_total = 0;
@@ -488,13 +528,36 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     next_slot(&q.bar, &q.abort_flag);
     return launch_qrcp_small(s, q);
   };
-  size_t goff = 0;   // offset of the current block's sketch in opts.G
+  // offset of block i's sketch in opts.G: every earlier block was sampled
+  auto goff_of = [&](int64_t i) {
+    size_t off = 0;
+    for (int64_t j = 0; j < i; ++j) off += (size_t)ks * (m - j * b);
+    return off;
+  };
+  // Overlapped schedule (FP64, permutation pivots).  The sketch of block i+1
+  // is Y_{i+1} = G_{i+1} C'(b_i:, :) with C' = C - (V T^T) W the updated
+  // trailing matrix; it equals G_{i+1} C(b_i:, :) - (G_{i+1} (V T^T)(b_i:, :)) W,
+  // whose first product reads C before the update and runs on the auxiliary
+  // stream during the panel, and whose correction is two thin products on
+  // the main stream.  The trailing update of block i then runs on the
+  // auxiliary stream during the pivoted QR of block i+1, and block i+1's
+  // column moves wait for it.  (Same quantity, other rounding order.)
+  bool y_ready = false;       // Y already holds this block's sketch product
+  bool upd_pending = false;   // the previous block's update runs on the auxiliary stream
+  auto join_update = [&]() -> hipError_t {
+    if (!upd_pending) return hipSuccess;
+    upd_pending = false;
+    return hipStreamWaitEvent(s, h->ev_upd, 0);
+  };
 
   for (int64_t i = 0; i < P.nblocks; ++i) {
     const int64_t r0 = i * b, bi = std::min(b, P.k - r0), mi = m - r0, ni = n - r0;
     T *X = A + r0 + r0 * lda;
+    const bool pipe_next =
+        aux && !P.fixed && i + 1 < P.nblocks && !block_is_classical_tail(P, i + 1) && ni > bi;
     if (!P.fixed) {
       if (block_is_classical_tail(P, i)) {
+        CHK(join_update(), "wait for the trailing update");
         // last block of Fig. 3: classical QRCP of the remaining block
         {
           ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)mi, (double)ni, (double)bi), 16.0 * mi * ni);
@@ -505,40 +568,43 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
             "move columns");
       } else {
-        const double *Gi;
-        if (o->G) {
-          Gi = o->G + goff;
-        } else {
-          ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mi);
-          CHK(launch_sketch(s, o->seed, i, ks, r0, mi, G, ks), "sketch");
-          Gi = G;
-        }
-        goff += (size_t)ks * mi;
-        // Y_i = G_i X_i (Section 4.1, eq. defY).  The orthonormal variant runs
-        // the QR of Y_i^T without pivoting, whose first b_i reflectors depend
-        // only on the first b_i rows of Y_i: only those are formed.
         const int64_t yrows = P.ortho ? bi : ks;
-        {
-          ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * yrows * ni * mi,
-                         (double)sizeof(T) * mi * ni + 8.0 * (yrows * mi + yrows * ni));
-          if constexpr (!F32) {
-            GemmF64 gy{false, false, yrows, ni, mi, Gi, ks, X, lda, Y, ks, 1.0, 0.0};
-            CHK(launch_gemm_f64(s, gy, gpart), "sketch product");
-          } else if (P.mixed) {
-            CHK(launch_g_to_bf16(s, Gi, ks, yrows, mi, Gb, mi), "sketch to BF16");
-            CHK(launch_sample_bf16(s, yrows, ni, mi, Gb, mi, X, lda, spart, Y, ks), "BF16 sketch product");
+        if (!y_ready) {
+          const double *Gi;
+          if (o->G) {
+            Gi = o->G + goff_of(i);
           } else {
-            CHK(launch_copy_f64_f32(s, Gi, ks, G32, ks, yrows, mi), "sketch to FP32");
-            GemmF32 gy{false, false, yrows, ni, mi, G32, ks, X, lda, Y32, ks, 1.f, 0.f};
-            CHK(launch_gemm<float>(s, gy, gpart32), "FP32 sketch product");
-            CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
+            ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mi);
+            CHK(launch_sketch(s, o->seed, i, ks, r0, mi, G, ks), "sketch");
+            Gi = G;
+          }
+          // Y_i = G_i X_i (Section 4.1, eq. defY).  The orthonormal variant runs
+          // the QR of Y_i^T without pivoting, whose first b_i reflectors depend
+          // only on the first b_i rows of Y_i: only those are formed.
+          {
+            ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * yrows * ni * mi,
+                           (double)sizeof(T) * mi * ni + 8.0 * (yrows * mi + yrows * ni));
+            if constexpr (!F32) {
+              GemmF64 gy{false, false, yrows, ni, mi, Gi, ks, X, lda, Y, ks, 1.0, 0.0};
+              CHK(launch_gemm_f64(s, gy, gpart), "sketch product");
+            } else if (P.mixed) {
+              CHK(launch_g_to_bf16(s, Gi, ks, yrows, mi, Gb, mi), "sketch to BF16");
+              CHK(launch_sample_bf16(s, yrows, ni, mi, Gb, mi, X, lda, spart, Y, ks), "BF16 sketch product");
+            } else {
+              CHK(launch_copy_f64_f32(s, Gi, ks, G32, ks, yrows, mi), "sketch to FP32");
+              GemmF32 gy{false, false, yrows, ni, mi, G32, ks, X, lda, Y32, ks, 1.f, 0.f};
+              CHK(launch_gemm<float>(s, gy, gpart32), "FP32 sketch product");
+              CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
+            }
           }
         }
+        y_ready = false;
         if (!P.ortho) {
           {
             ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)ks, (double)ni, (double)bi), 8.0 * ks * ni);
             CHK(run_qrcp(Y, ks, ks, ni, bi, i), "pivoted QR of the sketch");
           }
+          CHK(join_update(), "wait for the trailing update");
           ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 32.0 * bi * m);
           CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
               "move columns");
@@ -577,6 +643,29 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           }
         }
       }
+    }
+    // next block's sketch and the product G_{i+1} C(b_i:, :) on the auxiliary
+    // stream: C is final here (moved, not yet updated), and the panel does
+    // not touch it
+    const double *Gn = nullptr;
+    if constexpr (!F32) if (pipe_next) {
+      CHK(hipEventRecord(h->ev_moves, s), "fork event");
+      CHK(hipStreamWaitEvent(aux, h->ev_moves, 0), "auxiliary stream wait");
+      const int64_t mn = mi - bi, nn = ni - bi;
+      if (o->G) {
+        Gn = o->G + goff_of(i + 1);
+      } else {
+        ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mn, aux);
+        CHK(launch_sketch(aux, o->seed, i + 1, ks, r0 + bi, mn, G, ks, h->aux_wg), "sketch");
+        Gn = G;
+      }
+      {
+        ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * nn * mn, 8.0 * (mn * nn + ks * mn + ks * nn), aux);
+        GemmF64 gy{false, false, ks, nn, mn, Gn, ks, X + bi + bi * lda, lda, Y, ks, 1.0, 0.0};
+        gy.max_wg = h->aux_wg;
+        CHK(launch_gemm_f64(aux, gy, gpart_aux), "sketch product of the next block");
+      }
+      CHK(hipEventRecord(h->ev_ypre, aux), "sketch product event");
     }
     // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi) in FP64
     {
@@ -632,7 +721,30 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
         if constexpr (F32) CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
       }
-      {
+      if (pipe_next) {
+        if constexpr (!F32) {
+          // the update on the auxiliary stream, the next sketch's correction here
+          CHK(hipEventRecord(h->ev_vt, s), "update fork event");
+          CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
+          {
+            ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
+                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+            GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0, true};
+            gu.max_wg = h->aux_wg;
+            CHK(launch_gemm_f64(aux, gu, gpart_aux), "C -= (V T^T) W");
+          }
+          CHK(hipEventRecord(h->ev_upd, aux), "update event");
+          upd_pending = true;
+          CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product");
+          const int64_t mn = mi - bi;
+          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * (mn + nc), 8.0 * (ks * mn + 2.0 * ks * nc + bi * nc));
+          GemmF64 g1{false, false, ks, bi, mn, Gn, ks, Vt + bi, mi, GVb, ks, 1.0, 0.0};
+          CHK(launch_gemm_f64(s, g1, gpart), "G (V T^T)");
+          GemmF64 g2{false, false, ks, ni - bi, bi, GVb, ks, Wb, bi, Y, ks, -1.0, 1.0};
+          CHK(launch_gemm_f64(s, g2, gpart), "Y -= (G V T^T) W");
+          y_ready = true;
+        }
+      } else {
         ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
                        (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
@@ -645,6 +757,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       }
     }
   }
+  CHK(join_update(), "wait for the trailing update");
   (void)piv;
   return RQRCP_OK;
 }

@@ -187,7 +187,7 @@ __device__ __forceinline__ bool grid_sync(const GridBarrier &gb, unsigned &gen, 
 
 // Gaussian sketch: G(r, g - row0) for r < nsample, g in [row0, row0 + nrows).
 hipError_t launch_sketch(hipStream_t s, uint64_t seed, int64_t block, int64_t nsample, int64_t row0,
-                         int64_t nrows, double *G, int64_t ldg);
+                         int64_t nrows, double *G, int64_t ldg, int max_wg = 0);
 
 // C = alpha op(A) op(B) + beta C on the matrix cores (FP64 or FP32), column-major.  When the
 // problem is split along K the partial products go to `partial` (at least
@@ -201,6 +201,8 @@ struct Gemm {
   T *C; int64_t ldc;
   T alpha, beta;
   bool trailing = false;   // the factorization's trailing update (a separate kernel name in profiles)
+  int max_wg = 0;          // > 0: at most this many workgroups (each loops over tiles), so that a
+                           // product on a side stream leaves CUs free for persistent kernels
 };
 typedef Gemm<double> GemmF64;
 typedef Gemm<float> GemmF32;

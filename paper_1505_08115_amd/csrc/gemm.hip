@@ -16,6 +16,8 @@
 //  * Split-K: when the M x N tile grid is too small to fill 256 CUs, K is cut
 //    into slabs whose partial products are summed in a fixed order by a
 //    second kernel, so results do not depend on scheduling.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rq {
@@ -65,12 +67,11 @@ template <> struct Mfma<float> {
 // tiles on full K slabs load without bounds checks.  Two LDS stages: the
 // next slab is written to the other stage while this one feeds the MFMAs,
 // one barrier per K slab.
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
-__global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
-                                                      const T *__restrict__ A, int64_t lda,
-                                                      const T *__restrict__ B, int64_t ldb,
-                                                      T *__restrict__ C, int64_t ldc, T alpha,
-                                                      T beta, T *__restrict__ partial) {
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT>
+__device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64_t kchunk, const T *__restrict__ A,
+                                          int64_t lda, const T *__restrict__ B, int64_t ldb, T *__restrict__ C,
+                                          int64_t ldc, T alpha, T beta, T *__restrict__ partial, int64_t m0,
+                                          int64_t n0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int AE = BM * kBK / 256, BE = BN * kBK / 256;
@@ -82,7 +83,6 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
   const bool interior = m0 + BM <= M && n0 + BN <= N;
@@ -177,6 +177,34 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
   }
 }
 
+// One tile per workgroup (blockIdx.x, blockIdx.y).  TRAIL only gives the
+// factorization's trailing update a kernel name of its own in profiles.
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
+__global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                      const T *__restrict__ A, int64_t lda,
+                                                      const T *__restrict__ B, int64_t ldb,
+                                                      T *__restrict__ C, int64_t ldc, T alpha,
+                                                      T beta, T *__restrict__ partial) {
+  gemm_tile<T, BM, BN, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                      (int64_t)blockIdx.x * BM, (int64_t)blockIdx.y * BN);
+}
+
+// A capped grid: each workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... of the tile grid in column-major order (each tile's K loop ends with a
+// barrier, so the LDS stages are free for the next tile).  A capped grid has
+// about one workgroup per CU, so the register budget is that of one.
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
+__global__ __launch_bounds__(256, 1) void gemm_kernel_capped(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                             const T *__restrict__ A, int64_t lda,
+                                                             const T *__restrict__ B, int64_t ldb,
+                                                             T *__restrict__ C, int64_t ldc, T alpha,
+                                                             T beta, T *__restrict__ partial) {
+  const int64_t ntm = (M + BM - 1) / BM, ntiles = ntm * ((N + BN - 1) / BN);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    gemm_tile<T, BM, BN, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                        (tile % ntm) * BM, (tile / ntm) * BN);
+}
+
 // Short, wide products C (M x N) = alpha op(A) B + beta C with M <= 448 (the
 // sketch Y = G X and W = V^T C): one workgroup holds all M rows of a
 // 128-column slab of C, so the large operand B is read from HBM exactly once
@@ -187,11 +215,10 @@ constexpr int kRowsBN = 128;
 constexpr int kRowsThreads = 512;
 
 template <typename T, int MT, bool TA, bool SPLIT>
-__global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
-                                                                 const T *__restrict__ A, int64_t lda,
-                                                                 const T *__restrict__ B, int64_t ldb,
-                                                                 T *__restrict__ C, int64_t ldc, T alpha, T beta,
-                                                                 T *__restrict__ partial) {
+__device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                               const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
+                                               int64_t ldb, T *__restrict__ C, int64_t ldc, T alpha, T beta,
+                                               T *__restrict__ partial, int64_t n0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int MP = 16 * MT;                                   // padded rows
   constexpr int AE = (MP * kBK + kRowsThreads - 1) / kRowsThreads;
@@ -200,7 +227,6 @@ __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int6
   __shared__ T Bs[2][kBK][kRowsBN + kPad];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t n0 = (int64_t)blockIdx.x * kRowsBN;
   const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
   const bool interior = n0 + kRowsBN <= N;
@@ -280,6 +306,28 @@ __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int6
   }
 }
 
+template <typename T, int MT, bool TA, bool SPLIT>
+__global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                                 const T *__restrict__ A, int64_t lda,
+                                                                 const T *__restrict__ B, int64_t ldb,
+                                                                 T *__restrict__ C, int64_t ldc, T alpha, T beta,
+                                                                 T *__restrict__ partial) {
+  gemm_rows_slab<T, MT, TA, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                   (int64_t)blockIdx.x * kRowsBN);
+}
+
+// A capped grid: slabs blockIdx.x, blockIdx.x + gridDim.x, ... of 128 columns.
+template <typename T, int MT, bool TA, bool SPLIT>
+__global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel_capped(int64_t M, int64_t N, int64_t K,
+                                                                        int64_t kchunk, const T *__restrict__ A,
+                                                                        int64_t lda, const T *__restrict__ B,
+                                                                        int64_t ldb, T *__restrict__ C, int64_t ldc,
+                                                                        T alpha, T beta, T *__restrict__ partial) {
+  const int64_t nslab = (N + kRowsBN - 1) / kRowsBN;
+  for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x)
+    gemm_rows_slab<T, MT, TA, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial, sl * kRowsBN);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t N, int splits,
                                                               const T *__restrict__ partial,
@@ -298,6 +346,20 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t
 
 template <typename T, int BM, int BN, bool TA, bool TB>
 hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+  const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  if (g.max_wg > 0 && tiles * splits > g.max_wg) {
+    dim3 cg((unsigned)std::max<int64_t>(1, g.max_wg / splits), 1, (unsigned)splits);
+    if (splits > 1)
+      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, true>), cg, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
+                         g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    else if (g.trailing && !TA && !TB)
+      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, false, false, false, true>), cg, dim3(256), 0, s, g.M, g.N,
+                         g.K, kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    else
+      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, false>), cg, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
+                         g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)splits);
   if (splits > 1)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, true>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
@@ -366,7 +428,8 @@ constexpr int64_t kRowsSlots = 256;
 template <typename T>
 void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   const int64_t tiles = (g.N + kRowsBN - 1) / kRowsBN;
-  int64_t sp = kRowsSlots / tiles;                           // tiles * splits <= one round
+  const int64_t slots = g.max_wg > 0 ? std::min<int64_t>(g.max_wg, kRowsSlots) : kRowsSlots;
+  int64_t sp = slots / tiles;                                // tiles * splits <= one round
   const int64_t maxsp = g.K / (kBK * 16);                    // at least 256 of K per split
   if (sp > maxsp) sp = maxsp;
   if (sp > 64) sp = 64;
@@ -381,7 +444,18 @@ void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
 
 template <typename T, int MT, bool TA>
 hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
-  dim3 grid((unsigned)((g.N + kRowsBN - 1) / kRowsBN), (unsigned)splits);
+  const int64_t slabs = (g.N + kRowsBN - 1) / kRowsBN;
+  if (g.max_wg > 0 && slabs * splits > g.max_wg) {
+    dim3 cg((unsigned)std::max<int64_t>(1, g.max_wg / splits), (unsigned)splits);
+    if (splits > 1)
+      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, true>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    else
+      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, false>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)slabs, (unsigned)splits);
   if (splits > 1)
     hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, true>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K, kchunk,
                        g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
@@ -432,6 +506,7 @@ hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial) {
   const int64_t MN = g.M * g.N;
   int64_t grid = (MN + 255) / 256;
   if (grid > 8192) grid = 8192;
+  if (g.max_wg > 0 && grid > g.max_wg) grid = g.max_wg;
   hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits, partial,
                      g.C, g.ldc, g.alpha, g.beta);
   return hipGetLastError();

@@ -50,11 +50,12 @@ __global__ __launch_bounds__(256) void sketch_kernel(double *__restrict__ G, int
 }  // namespace
 
 hipError_t launch_sketch(hipStream_t s, uint64_t seed, int64_t block, int64_t nsample, int64_t row0,
-                         int64_t nrows, double *G, int64_t ldg) {
+                         int64_t nrows, double *G, int64_t ldg, int max_wg) {
   const int64_t total = nsample * nrows;
   if (total <= 0) return hipSuccess;
   int64_t grid = (total + 255) / 256;
   if (grid > 65536) grid = 65536;
+  if (max_wg > 0 && grid > max_wg) grid = max_wg;
   hipLaunchKernelGGL(sketch_kernel, dim3((unsigned)grid), dim3(256), 0, s, G, ldg, nsample, nrows, row0,
                      (uint64_t)block, seed);
   return hipGetLastError();
