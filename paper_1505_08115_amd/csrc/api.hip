@@ -707,6 +707,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
           GemmF64 gw{false, false, bi, ni - bi, mi, VT, b, C, lda, Wb, bi, 1.0, 0.0};
+          gw.wprod = true;
           CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
         } else {
           CHK(launch_copy_f64_f32(s, VT, b, VT32, b, bi, mi), "V^T to FP32");

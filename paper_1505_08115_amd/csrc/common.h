@@ -203,6 +203,7 @@ struct Gemm {
   bool trailing = false;   // the factorization's trailing update (a separate kernel name in profiles)
   int max_wg = 0;          // > 0: at most this many workgroups (each loops over tiles), so that a
                            // product on a side stream leaves CUs free for persistent kernels
+  bool wprod = false;      // the factorization's W = V^T C (a separate kernel name in profiles)
 };
 typedef Gemm<double> GemmF64;
 typedef Gemm<float> GemmF32;

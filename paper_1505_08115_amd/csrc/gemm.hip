@@ -57,10 +57,7 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int drow(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// TRAIL only renames the trailing-update instance (C -= (V T^T) W) so that
-// profiles show it as a kernel of its own.
-//
-// Each thread prefetches AE elements of the A slab and BE of the B slab; the
+// One 128 x 128 (or 64-wide) tile of C.  Each thread prefetches AE elements of the A slab and BE of the B slab; the
 // elements of one thread sit at a fixed base plus a uniform stride (the
 // flattened index t + 256 q maps to (t mod L) and (t / L) + q 256/L along the
 // contiguous dimension L), so no per-element addresses stay live.  Interior
@@ -177,9 +174,10 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64
   }
 }
 
-// One tile per workgroup (blockIdx.x, blockIdx.y).  TRAIL only gives the
-// factorization's trailing update a kernel name of its own in profiles.
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
+// One tile per workgroup (blockIdx.x, blockIdx.y).  TAG only gives two of
+// the factorization's products kernel names of their own in profiles:
+// kTagTrail for the trailing update C -= (V T^T) W, kTagW for W = V^T C.
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int TAG = 0>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                       const T *__restrict__ A, int64_t lda,
                                                       const T *__restrict__ B, int64_t ldb,
@@ -193,7 +191,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
 // ... of the tile grid in column-major order (each tile's K loop ends with a
 // barrier, so the LDS stages are free for the next tile).  A capped grid has
 // about one workgroup per CU, so the register budget is that of one.
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, bool TRAIL = false>
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int TAG = 0>
 __global__ __launch_bounds__(256, 1) void gemm_kernel_capped(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                              const T *__restrict__ A, int64_t lda,
                                                              const T *__restrict__ B, int64_t ldb,
@@ -212,6 +210,7 @@ __global__ __launch_bounds__(256, 1) void gemm_kernel_capped(int64_t M, int64_t 
 // threads = 8 waves, wave w owns columns 16w .. 16w+15 of the slab and all
 // MT row blocks of 16; K is split over workgroups to fill the chip.
 constexpr int kRowsBN = 128;
+constexpr int kTagTrail = 1, kTagW = 2;   // kernel-name tags (profiles only)
 constexpr int kRowsThreads = 512;
 
 template <typename T, int MT, bool TA, bool SPLIT>
@@ -306,7 +305,7 @@ __device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, 
   }
 }
 
-template <typename T, int MT, bool TA, bool SPLIT>
+template <typename T, int MT, bool TA, bool SPLIT, int TAG = 0>
 __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                                  const T *__restrict__ A, int64_t lda,
                                                                  const T *__restrict__ B, int64_t ldb,
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel_capped(int64_t 
     gemm_rows_slab<T, MT, TA, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial, sl * kRowsBN);
 }
 
-template <typename T>
+template <typename T, int TAG = 0>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t N, int splits,
                                                               const T *__restrict__ partial,
                                                               T *__restrict__ C, int64_t ldc,
@@ -344,37 +343,36 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t
   }
 }
 
-template <typename T, int BM, int BN, bool TA, bool TB>
-hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+template <typename T, int BM, int BN, bool TA, bool TB, int TAG>
+hipError_t launch_tiles_tag(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   if (g.max_wg > 0 && tiles * splits > g.max_wg) {
     dim3 cg((unsigned)std::max<int64_t>(1, g.max_wg / splits), 1, (unsigned)splits);
     if (splits > 1)
-      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, true>), cg, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
-                         g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
-    else if (g.trailing && !TA && !TB)
-      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, false, false, false, true>), cg, dim3(256), 0, s, g.M, g.N,
-                         g.K, kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, true, TAG>), cg, dim3(256), 0, s, g.M, g.N, g.K,
+                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
     else
-      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, false>), cg, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
-                         g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+      hipLaunchKernelGGL((gemm_kernel_capped<T, BM, BN, TA, TB, false, TAG>), cg, dim3(256), 0, s, g.M, g.N, g.K,
+                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)splits);
   if (splits > 1)
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, true>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
-                       g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
-  else if constexpr (!TA && !TB) {
-    if (g.trailing)
-      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, false, false, false, true>), grid, dim3(256), 0, s, g.M, g.N, g.K,
-                         kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
-    else
-      hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
-                         g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
-  } else
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk, g.A,
-                       g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, true, TAG>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
+                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA, TB, false, TAG>), grid, dim3(256), 0, s, g.M, g.N, g.K, kchunk,
+                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   return hipGetLastError();
+}
+
+template <typename T, int BM, int BN, bool TA, bool TB>
+hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+  if constexpr (!TA && !TB) {
+    if (g.trailing) return launch_tiles_tag<T, BM, BN, false, false, kTagTrail>(s, g, splits, kchunk, partial);
+    if (g.wprod) return launch_tiles_tag<T, BM, BN, false, false, kTagW>(s, g, splits, kchunk, partial);
+  }
+  return launch_tiles_tag<T, BM, BN, TA, TB, 0>(s, g, splits, kchunk, partial);
 }
 
 template <typename T, bool TA, bool TB>
@@ -442,8 +440,8 @@ void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   *kchunk = kc;
 }
 
-template <typename T, int MT, bool TA>
-hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+template <typename T, int MT, bool TA, int TAG>
+hipError_t launch_rows_tag(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   const int64_t slabs = (g.N + kRowsBN - 1) / kRowsBN;
   if (g.max_wg > 0 && slabs * splits > g.max_wg) {
     dim3 cg((unsigned)std::max<int64_t>(1, g.max_wg / splits), (unsigned)splits);
@@ -457,12 +455,18 @@ hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t k
   }
   dim3 grid((unsigned)slabs, (unsigned)splits);
   if (splits > 1)
-    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, true>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K, kchunk,
-                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, true, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+                       kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   else
-    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, false>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K, kchunk,
-                       g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, false, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+                       kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   return hipGetLastError();
+}
+
+template <typename T, int MT, bool TA>
+hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
+  if (g.wprod) return launch_rows_tag<T, MT, TA, kTagW>(s, g, splits, kchunk, partial);
+  return launch_rows_tag<T, MT, TA, 0>(s, g, splits, kchunk, partial);
 }
 
 template <typename T, bool TA>
@@ -507,8 +511,12 @@ hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial) {
   int64_t grid = (MN + 255) / 256;
   if (grid > 8192) grid = 8192;
   if (g.max_wg > 0 && grid > g.max_wg) grid = g.max_wg;
-  hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits, partial,
-                     g.C, g.ldc, g.alpha, g.beta);
+  if (g.wprod)
+    hipLaunchKernelGGL((reduce_partials_kernel<T, kTagW>), dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits,
+                       partial, g.C, g.ldc, g.alpha, g.beta);
+  else
+    hipLaunchKernelGGL((reduce_partials_kernel<T, 0>), dim3((unsigned)grid), dim3(256), 0, s, g.M, g.N, splits,
+                       partial, g.C, g.ldc, g.alpha, g.beta);
   return hipGetLastError();
 }
 

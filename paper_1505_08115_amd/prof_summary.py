@@ -10,8 +10,9 @@
 factorization.  `pmc` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
 counter runs (KiB per dispatch), scales each counter by what it reads for the
 calibration kernel (the driver's calib_copy_kernel over 2^26 doubles: 2^29
-bytes read, 2^29 bytes written), and reports the HBM bytes per trailing-update launch next to
-the algorithmic bytes 8 (2 m_i n_i + m_i b + b n_i) of each launch.
+bytes read, 2^29 bytes written), and reports the HBM bytes per W = V^T C
+launch (the product kernel and its split-K sum) next to the algorithmic bytes
+8 (m_i n_c + b m_i + b n_c) of each launch (n_c = n_i - b).
 """
 import argparse
 import csv
@@ -22,7 +23,9 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GEMM_SOURCES = ("paper_1505_08115_amd/csrc/gemm.hip",)   # the file that defines the GEMM kernels
-TRAIL = re.compile(r"gemm_kernel<double, \d+, \d+, false, false, false, true>")
+# kernels tagged 2 (W = V^T C): the all-rows or tiled product and the split-K sum
+WMAIN = re.compile(r"(gemm_rows_kernel<double, \d+, false, (true|false), 2>|gemm_kernel<double, \d+, \d+, false, false, (true|false), 2>)")
+WSUM = re.compile(r"reduce_partials_kernel<double, 2>")
 CALIB = "calib_copy_kernel"
 CALIB_BYTES = 1 << 29
 
@@ -72,15 +75,16 @@ def pmc(args):
             key = (r["Dispatch_Id"], r["Kernel_Name"])
             by[key] = by.get(key, 0.0) + float(r["Counter_Value"])
         cal = [v for (d, k), v in by.items() if CALIB in k]
-        trail = [v for (d, k), v in by.items() if TRAIL.search(k)]
-        if not cal or not trail:
-            sys.exit(f"{path}: calibration or trailing-update dispatches missing")
+        wmain = [v for (d, k), v in by.items() if WMAIN.search(k)]
+        wsum = [v for (d, k), v in by.items() if WSUM.search(k)]
+        if not cal or not wmain:
+            sys.exit(f"{path}: calibration or W-product dispatches missing")
         scale = CALIB_BYTES / (cal[-1] * 1024.0)
-        res[counter] = (cal[-1], scale, len(trail), sum(trail))
+        res[counter] = (cal[-1], scale, len(wmain), sum(wmain) + sum(wsum))
     n_tr = res["FETCH_SIZE"][2]
     fetch_b = res["FETCH_SIZE"][3] * 1024.0 * res["FETCH_SIZE"][1]
     write_b = res["WRITE_SIZE"][3] * 1024.0 * res["WRITE_SIZE"][1]
-    # algorithmic bytes of the trailing updates of one factorization (m = n = 8192, b = 256)
+    # algorithmic bytes of the W products of one factorization (m = n = 8192, b = 256)
     m = n = args.n
     b = args.block
     alg = 0.0
@@ -91,10 +95,10 @@ def pmc(args):
         nc = ni - bi
         if nc <= 0:
             continue
-        alg += 8.0 * (2.0 * mi * nc + mi * bi + bi * nc)
+        alg += 8.0 * (mi * nc + mi * bi + bi * nc)
         launches += 1
     per_launch = (fetch_b + write_b) / n_tr
-    out = ["# rocprofv3 HBM counters, trailing-update GEMM (C -= (V T^T) W) at the H1 shape (8192^2, b=256, p=10, FP64)",
+    out = ["# rocprofv3 HBM counters, W = V^T C (product + split-K sum) at the H1 shape (8192^2, b=256, p=10, FP64)",
            f"command (fetch): {args.command_fetch}",
            f"command (write): {args.command_write}",
            f"calibration kernel: {CALIB} over 2^26 doubles ({CALIB_BYTES} B read, {CALIB_BYTES} B written)",
@@ -102,7 +106,7 @@ def pmc(args):
            f"calibration WRITE_SIZE KiB: {res['WRITE_SIZE'][0]:.0f}",
            f"scale_fetch: {res['FETCH_SIZE'][1]:.4f}",
            f"scale_write: {res['WRITE_SIZE'][1]:.4f}",
-           f"trailing-update dispatches: {n_tr} ({n_tr / f:.0f} per factorization)",
+           f"W launches: {n_tr} ({n_tr / f:.0f} per factorization)",
            f"fetch_bytes_per_launch (scaled): {fetch_b / n_tr:.4e}",
            f"write_bytes_per_launch (scaled): {write_b / n_tr:.4e}",
            f"traffic_bytes_per_launch: {per_launch:.6e}",
