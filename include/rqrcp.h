@@ -188,6 +188,7 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
  * T: a factorization of A with rank >= k (e.g. recomputed with fixed_pivots).
  * dAk (in) m x n, ld ldg; dA (out) m x n, ld ldda.  All of type dt (F32:
  * widened to FP64 in the workspace, computed in FP64, dA rounded to FP32).
+ * k <= 8192 (RQRCP_ERR_UNSUPPORTED beyond).
  * work: at least rqrcp_lowrank_backward_work_bytes bytes. */
 size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n,

@@ -1128,6 +1128,7 @@ rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
+  if (k > 8192) return fail(h, RQRCP_ERR_UNSUPPORTED, "k: at most 8192 in the backward of this build");
   if (!Av || !VR || !jpvt || !T || !dAkv || !dAv) return fail(h, RQRCP_ERR_ARG, "a required pointer is NULL");
   if (lda < m || ldvr < m || ldg < m || ldda < m) return fail(h, RQRCP_ERR_ARG, "leading dimensions must be >= m");
   if (!work || work_bytes < rqrcp_lowrank_backward_work_bytes(dt, m, n, k, b))

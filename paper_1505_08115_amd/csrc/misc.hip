@@ -97,18 +97,27 @@ __global__ void iota_kernel(int32_t *__restrict__ p, int64_t n) {
 }
 
 // Rinv = R^{-1} for an upper-triangular k x k R: column j solves R x = e_j by
-// back substitution (one thread per column).
-__global__ void tri_inv_upper_kernel(const double *__restrict__ R, int64_t ldr, int64_t k, double *__restrict__ Ri,
-                                     int64_t ldi) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  double *x = Ri + j * ldi;
-  for (int64_t i = k - 1; i > j; --i) x[i] = 0.0;
+// back substitution in column order, one workgroup per column, x in LDS:
+// for i = j, j-1, ..., 0: x_i /= R_ii, then x_{0:i} -= x_i R_{0:i,i} with the
+// threads spread over the rows (each step reads one column of R, coalesced;
+// the next step's column is loaded while this one is applied).
+constexpr int kTriThreads = 256;
+__global__ __launch_bounds__(kTriThreads) void tri_inv_upper_kernel(const double *__restrict__ R, int64_t ldr,
+                                                                    int64_t k, double *__restrict__ Ri, int64_t ldi) {
+  extern __shared__ double x[];
+  const int64_t j = blockIdx.x;
+  const int t = threadIdx.x;
+  for (int64_t r = t; r < k; r += kTriThreads) x[r] = r == j ? 1.0 : 0.0;
+  __syncthreads();
   for (int64_t i = j; i >= 0; --i) {
-    double acc = (i == j) ? 1.0 : 0.0;
-    for (int64_t q = i + 1; q <= j; ++q) acc -= R[i + q * ldr] * x[q];
-    x[i] = acc / R[i + i * ldr];
+    const double xi = x[i] / R[i + i * ldr];
+    __syncthreads();   // every thread has read x[i] before it changes
+    if (t == 0) x[i] = xi;
+    const double *col = R + i * ldr;
+    for (int64_t r = t; r < i; r += kTriThreads) x[r] -= xi * col[r];
+    __syncthreads();
   }
+  for (int64_t r = t; r < k; r += kTriThreads) Ri[r + j * ldi] = x[r];
 }
 
 template <typename S, typename D>
@@ -205,7 +214,9 @@ hipError_t launch_scatter_cols_f32(hipStream_t s, const float *src, int64_t lds,
 }
 hipError_t launch_tri_inv_upper(hipStream_t s, const double *R, int64_t ldr, int64_t k, double *Ri, int64_t ldi) {
   if (k <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s, R, ldr, k, Ri, ldi);
+  const size_t lds = (size_t)k * sizeof(double);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;   // at most 8192 columns
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((unsigned)k), dim3(kTriThreads), (unsigned)lds, s, R, ldr, k, Ri, ldi);
   return hipGetLastError();
 }
 
