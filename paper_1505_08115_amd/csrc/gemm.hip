@@ -57,29 +57,33 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int drow(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// One 128 x 128 (or 64-wide) tile of C.  Each thread prefetches AE elements of the A slab and BE of the B slab; the
-// elements of one thread sit at a fixed base plus a uniform stride (the
-// flattened index t + 256 q maps to (t mod L) and (t / L) + q 256/L along the
-// contiguous dimension L), so no per-element addresses stay live.  Interior
+// One BM x BN tile of C by NT threads: waves in a WGM x (NT/64/WGM) grid, each
+// owning a (BM/WGM) x (BN/WGN) block.  Each thread prefetches AE elements of
+// the A slab and BE of the B slab; the elements of one thread sit at a fixed
+// base plus a uniform stride (the flattened index t + NT q maps to (t mod L)
+// and (t / L) + q NT/L along the contiguous dimension L), so no per-element
+// addresses stay live.  Interior
 // tiles on full K slabs load without bounds checks.  Two LDS stages: the
 // next slab is written to the other stage while this one feeds the MFMAs,
 // one barrier per K slab.
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT>
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int NT = 256, int WGM = 2>
 __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64_t kchunk, const T *__restrict__ A,
                                           int64_t lda, const T *__restrict__ B, int64_t ldb, T *__restrict__ C,
                                           int64_t ldc, T alpha, T beta, T *__restrict__ partial, int64_t m0,
                                           int64_t n0) {
   typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int TM = BM / 32, TN = BN / 32;
-  constexpr int AE = BM * kBK / 256, BE = BN * kBK / 256;
+  constexpr int WGN = NT / 64 / WGM;
+  constexpr int WBM = BM / WGM, WBN = BN / WGN;   // one wave's block
+  constexpr int TM = WBM / 16, TN = WBN / 16;
+  constexpr int AE = BM * kBK / NT, BE = BN * kBK / NT;
   // per-thread element coordinates: (first index, step per q) along rows/cols and k
-  constexpr int A_QI = TA ? 256 / kBK : 0, A_QK = TA ? 0 : 256 / BM;
-  constexpr int B_QJ = TB ? 0 : 256 / kBK, B_QK = TB ? 256 / BN : 0;
+  constexpr int A_QI = TA ? NT / kBK : 0, A_QK = TA ? 0 : NT / BM;
+  constexpr int B_QJ = TB ? 0 : NT / kBK, B_QK = TB ? NT / BN : 0;
   __shared__ T As[2][kBK][BM + kPad];
   __shared__ T Bs[2][kBK][BN + kPad];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WGM, wn = wave / WGM;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
   const bool interior = m0 + BM <= M && n0 + BN <= N;
@@ -138,9 +142,9 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64
     for (int kk = 0; kk < kBK; kk += 4) {
       T xa[TN], yb[TM];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) xa[b] = Bs[st][kk + lk][wn * (BN / 2) + b * 16 + lr];
+      for (int b = 0; b < TN; ++b) xa[b] = Bs[st][kk + lk][wn * WBN + b * 16 + lr];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) yb[a] = As[st][kk + lk][wm * (BM / 2) + a * 16 + lr];
+      for (int a = 0; a < TM; ++a) yb[a] = As[st][kk + lk][wm * WBM + a * 16 + lr];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -154,13 +158,13 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64
 
 #pragma unroll
   for (int a = 0; a < TM; ++a) {
-    const int64_t row = m0 + wm * (BM / 2) + a * 16 + lr;
+    const int64_t row = m0 + wm * WBM + a * 16 + lr;
     if (row >= M) continue;
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t col = n0 + wn * (BN / 2) + b * 16 + Mfma<T>::drow(lane, r);
+        const int64_t col = n0 + wn * WBN + b * 16 + Mfma<T>::drow(lane, r);
         if (col >= N) continue;
         const T v = acc[a][b][r];
         if (SPLIT) {
@@ -191,16 +195,16 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
 // ... of the tile grid in column-major order (each tile's K loop ends with a
 // barrier, so the LDS stages are free for the next tile).  A capped grid has
 // about one workgroup per CU, so the register budget is that of one.
-template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int TAG = 0>
-__global__ __launch_bounds__(256, 1) void gemm_kernel_capped(int64_t M, int64_t N, int64_t K, int64_t kchunk,
-                                                             const T *__restrict__ A, int64_t lda,
-                                                             const T *__restrict__ B, int64_t ldb,
-                                                             T *__restrict__ C, int64_t ldc, T alpha,
-                                                             T beta, T *__restrict__ partial) {
+template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int TAG = 0, int NT = 256, int WGM = 2>
+__global__ __launch_bounds__(NT, 1) void gemm_kernel_capped(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                            const T *__restrict__ A, int64_t lda,
+                                                            const T *__restrict__ B, int64_t ldb,
+                                                            T *__restrict__ C, int64_t ldc, T alpha,
+                                                            T beta, T *__restrict__ partial) {
   const int64_t ntm = (M + BM - 1) / BM, ntiles = ntm * ((N + BN - 1) / BN);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    gemm_tile<T, BM, BN, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
-                                        (tile % ntm) * BM, (tile / ntm) * BN);
+    gemm_tile<T, BM, BN, TA, TB, SPLIT, NT, WGM>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                                 (tile % ntm) * BM, (tile / ntm) * BN);
 }
 
 // Short, wide products C (M x N) = alpha op(A) B + beta C with M <= 448 (the
@@ -369,6 +373,17 @@ hipError_t launch_tiles_tag(hipStream_t s, const Gemm<T> &g, int splits, int64_t
 template <typename T, int BM, int BN, bool TA, bool TB>
 hipError_t launch_tiles(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   if constexpr (!TA && !TB) {
+    // a capped FP64 trailing update: 256 x 128 tiles by 8 waves (two per
+    // SIMD, the same per-wave block as the uncapped kernel), so that one
+    // workgroup per CU still hides latency
+    if constexpr (BM == 128 && BN == 128 && sizeof(T) == 8)
+      if (g.trailing && g.max_wg > 0 && splits == 1 && g.M >= 256) {
+        const int64_t tiles = ((g.M + 255) / 256) * ((g.N + 127) / 128);
+        dim3 cg((unsigned)std::min<int64_t>(tiles, g.max_wg));
+        hipLaunchKernelGGL((gemm_kernel_capped<T, 256, 128, false, false, false, kTagTrail, 512, 4>), cg, dim3(512),
+                           0, s, g.M, g.N, g.K, kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
+        return hipGetLastError();
+      }
     if (g.trailing) return launch_tiles_tag<T, BM, BN, false, false, kTagTrail>(s, g, splits, kchunk, partial);
     if (g.wprod) return launch_tiles_tag<T, BM, BN, false, false, kTagW>(s, g, splits, kchunk, partial);
   }
