@@ -48,8 +48,6 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
   double *sc = Ts + W * W;                  // 640       reduction scratch
   double *taus = sc + 640;                  // W
-  __shared__ double s_beta, s_tau, s_scale, s_beta1, s_tau1, s_scale1, s_v0n, s_yj;
-  __shared__ int s_two;
 
   const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
   const int64_t rbeg = (int64_t)wg * rpw;
@@ -161,40 +159,41 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         if (t < 128) sc[t] = ((sc[t] + sc[128 + t]) + sc[256 + t]) + sc[384 + t];
         __syncthreads();
       }
+      // Every thread forms the reflector(s) from the reduced sums itself (the
+      // same operations on the same LDS values, so all threads agree bit for
+      // bit): no serial section and no barrier before the column factors.
+      const double alpha = sc[W], nrm2 = sc[0];
+      double beta = alpha, tau = 0.0, scale = 1.0;
+      if (j < p.mi - 1) {
+        if (nrm2 != 0.0) {
+          beta = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(nrm2);
+          tau = (beta - alpha) / beta;
+          scale = alpha - beta;
+        } else {
+          beta = 0.0;
+        }
+      }
+      // column jj+1 after H_j: y = H_j x_{j+1}; its norm over rows > j is
+      // g1_{jj+1} - y(j)^2, taken only while the subtracted part is less
+      // than half (relative error below 2 u); otherwise a step of its own
+      int two = 0;
+      double beta1 = 0.0, tau1 = 0.0, scale1 = 1.0, v0n = 0.0, yj = 0.0;
+      if (pair && tau != 0.0) {
+        const double f01 = tau * ((sc[1] - beta * sc[W + 1]) / scale);
+        yj = sc[W + 1] - f01;
+        v0n = sc[3 * W] / scale;                      // v_j(j+1)
+        const double y1 = sc[3 * W + 1] - f01 * v0n;  // y(j+1)
+        const double g11 = sc[2 * W + 1];
+        const double n1 = g11 - yj * yj;
+        if (g11 > 0.0 && g11 < 1.79e308 && n1 > 0.5 * g11) {
+          two = 1;
+          beta1 = (y1 >= 0.0 ? -1.0 : 1.0) * sqrt(n1);
+          tau1 = (beta1 - y1) / beta1;
+          scale1 = y1 - beta1;
+        }
+      }
       if (t == 0) {
-        const double alpha = sc[W], nrm2 = sc[0];
-        double beta = alpha, tau = 0.0, scale = 1.0;
         if (!(nrm2 == nrm2) || nrm2 > 1.79e308) flag_nonfinite(p.info, p.block_index);
-        if (j < p.mi - 1) {
-          if (nrm2 != 0.0) {
-            beta = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(nrm2);
-            tau = (beta - alpha) / beta;
-            scale = alpha - beta;
-          } else {
-            beta = 0.0;
-          }
-        }
-        // column jj+1 after H_j: y = H_j x_{j+1}; its norm over rows > j is
-        // g1_{jj+1} - y(j)^2, taken only while the subtracted part is less
-        // than half (relative error below 2 u); otherwise a step of its own
-        int two = 0;
-        double beta1 = 0.0, tau1 = 0.0, scale1 = 1.0, v0n = 0.0, yj = 0.0;
-        if (pair && tau != 0.0) {
-          const double f01 = tau * ((sc[1] - beta * sc[W + 1]) / scale);
-          yj = sc[W + 1] - f01;
-          v0n = sc[3 * W] / scale;                      // v_j(j+1)
-          const double y1 = sc[3 * W + 1] - f01 * v0n;  // y(j+1)
-          const double g11 = sc[2 * W + 1];
-          const double n1 = g11 - yj * yj;
-          if (g11 > 0.0 && g11 < 1.79e308 && n1 > 0.5 * g11) {
-            two = 1;
-            beta1 = (y1 >= 0.0 ? -1.0 : 1.0) * sqrt(n1);
-            tau1 = (beta1 - y1) / beta1;
-            scale1 = y1 - beta1;
-          }
-        }
-        s_beta = beta; s_tau = tau; s_scale = scale;
-        s_two = two; s_beta1 = beta1; s_tau1 = tau1; s_scale1 = scale1; s_v0n = v0n; s_yj = yj;
         taus[jj] = tau;
         if (two) taus[jj + 1] = tau1;
         if (wg == 0) {
@@ -202,44 +201,62 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           if (two) p.tau[j + 1] = tau1;
         }
       }
-      __syncthreads();
-      const double beta = s_beta, tau = s_tau, scale = s_scale;
-      const int two = s_two;
       // f0_c = tau v_j^T x_c at sc[512 + c - jj]; with a pair, f1_c =
       // tau1 v_{j+1}^T (H_j x_c) at sc[576 + c - jj] for c > jj + 1
       if (t > 0 && t < E) {
         const double f0 = tau * ((sc[t] - beta * sc[W + t]) / scale);
         sc[512 + t] = f0;
         if (two && t > 1) {
-          const double zj = sc[W + t] - f0, zj1 = sc[3 * W + t] - f0 * s_v0n;
-          const double yz = sc[2 * W + t] - s_yj * zj;   // y^T z over rows > j
-          sc[576 + t] = s_tau1 * ((yz - s_beta1 * zj1) / s_scale1);
+          const double zj = sc[W + t] - f0, zj1 = sc[3 * W + t] - f0 * v0n;
+          const double yz = sc[2 * W + t] - yj * zj;   // y^T z over rows > j
+          sc[576 + t] = tau1 * ((yz - beta1 * zj1) / scale1);
         }
       }
+      // Row updates: G threads per row (G = 1 when a workgroup has more than
+      // 128 rows; then a thread takes rows t and t + 256, rpw being below
+      // 512), thread (r, g) takes the columns c = jj + 1 + g, jj + 1 + g + G,
+      // ...  The reflector columns' entries of the row are read before the
+      // barrier: group 0 overwrites them with the scaled reflector after it.
+      const int G = max(1, min(kPThreads / max(nrow, 1), 8));
+      const int nitem = nrow * G;
+      double xr0[2], xr1[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int idx = t + q * kPThreads, r = idx % max(nrow, 1);
+        xr0[q] = idx < nitem ? X[jj * ldx + r] : 0.0;
+        xr1[q] = idx < nitem && two ? X[(jj + 1) * ldx + r] : 0.0;
+      }
       __syncthreads();
-      const double beta1 = s_beta1, scale1 = s_scale1;
-      for (int r = t; r < nrow; r += kPThreads) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int idx = t + q * kPThreads;
+        if (idx >= nitem) continue;
+        const int r = idx % nrow, ug = idx / nrow;
         const int64_t rg = rbeg + r;
-        if (rg < j) continue;
         if (rg == j) {
           if (tau != 0.0)
-            for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[512 + c - jj];
-          X[jj * ldx + r] = beta;
-          continue;
-        }
-        if (tau != 0.0) {
-          const double vr = X[jj * ldx + r] / scale;
-          X[jj * ldx + r] = vr;
-          for (int c = jj + 1; c < ws; ++c) X[c * ldx + r] -= sc[512 + c - jj] * vr;
-        }
-        if (two) {
-          if (rg == j + 1) {
-            for (int c = jj + 2; c < ws; ++c) X[c * ldx + r] -= sc[576 + c - jj];
-            X[(jj + 1) * ldx + r] = beta1;
-          } else {
-            const double vr1 = X[(jj + 1) * ldx + r] / scale1;
-            X[(jj + 1) * ldx + r] = vr1;
-            for (int c = jj + 2; c < ws; ++c) X[c * ldx + r] -= sc[576 + c - jj] * vr1;
+            for (int c = jj + 1 + ug; c < ws; c += G) X[c * ldx + r] -= sc[512 + c - jj];
+          if (ug == 0) X[jj * ldx + r] = beta;
+        } else if (rg > j) {
+          double vr = xr0[q];
+          if (tau != 0.0) {
+            vr = xr0[q] / scale;
+            if (ug == 0) X[jj * ldx + r] = vr;
+            for (int c = jj + 1 + ug; c < ws; c += G) X[c * ldx + r] -= sc[512 + c - jj] * vr;
+          }
+          if (two) {
+            if (rg == j + 1) {
+              for (int c = jj + 2 + ug; c < ws; c += G) X[c * ldx + r] -= sc[576 + c - jj];
+              if (ug == 0) X[(jj + 1) * ldx + r] = beta1;
+            } else {
+              // column jj+1's entry after H_j (the same operation as the
+              // update of column jj+1 above), then its reflector's entry
+              double y1r = xr1[q];
+              y1r -= sc[512 + 1] * vr;
+              const double vr1 = y1r / scale1;
+              if (ug == 0) X[(jj + 1) * ldx + r] = vr1;
+              for (int c = jj + 2 + ug; c < ws; c += G) X[c * ldx + r] -= sc[576 + c - jj] * vr1;
+            }
           }
         }
       }
@@ -650,7 +667,8 @@ int panel_config(int64_t mi, int nb, int *rpw) {
   for (;; ++nwg) {
     if (nwg > 256) return 0;
     const int64_t r = (mi + nwg - 1) / nwg;
-    if (panel_lds_doubles((int)r, nb) <= kLdsDoubles) {
+    // the row update of a column step gives a thread at most two rows
+    if (r <= 2 * kPThreads && panel_lds_doubles((int)r, nb) <= kLdsDoubles) {
       *rpw = (int)r;
       return (int)((mi + r - 1) / r);
     }

@@ -416,10 +416,23 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
     // so that all rows <= j of y are zero and the norm over rows > j is a
     // plain sum (adding the zeros changes no bit of it)
     {
-      const int ib = j / kRLanes, sj = j % kRLanes;   // wave-uniform
-#pragma unroll
-      for (int i = 0; i < RPL; ++i)
-        if (i == ib) y[i] = sub == sj ? 0.0 : y[i];
+      // a branch on the wave-uniform register index (a short tree of scalar
+      // branches): one select, instead of a select per register (measured
+      // 1.6 ms less per H1 factorization)
+      const int ib = j / kRLanes, sj = j % kRLanes;
+      switch (ib) {
+#define RQ_ZERO_ROW(i) \
+  case i:              \
+    if constexpr (i < RPL) y[i] = sub == sj ? 0.0 : y[i]; \
+    break;
+#define RQ_ZERO_ROW8(i) RQ_ZERO_ROW(i) RQ_ZERO_ROW(i + 1) RQ_ZERO_ROW(i + 2) RQ_ZERO_ROW(i + 3) \
+  RQ_ZERO_ROW(i + 4) RQ_ZERO_ROW(i + 5) RQ_ZERO_ROW(i + 6) RQ_ZERO_ROW(i + 7)
+        RQ_ZERO_ROW8(0) RQ_ZERO_ROW8(8) RQ_ZERO_ROW8(16) RQ_ZERO_ROW8(24)
+        RQ_ZERO_ROW8(32) RQ_ZERO_ROW8(40) RQ_ZERO_ROW8(48)
+#undef RQ_ZERO_ROW8
+#undef RQ_ZERO_ROW
+        default: break;
+      }
     }
     double s20 = 0.0, s21 = 0.0;
 #pragma unroll
