@@ -233,32 +233,56 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         if (idx >= nitem) continue;
         const int r = idx % nrow, ug = idx / nrow;
         const int64_t rg = rbeg + r;
+        if (rg < j) continue;
+        // the row's multipliers: entry c gets x_c -= a0 f0_c (c > jj, when
+        // tau != 0), then x_c -= a1 f1_c (c > jj + 1, rows > j of a pair),
+        // the two updates of the column-by-column form in their order;
+        // a0 = v_j(r), a1 = v_{j+1}(r)
+        const bool do0 = tau != 0.0, do1 = two && rg > j;
+        double a0 = 0.0, a1 = 0.0;
         if (rg == j) {
-          if (tau != 0.0)
-            for (int c = jj + 1 + ug; c < ws; c += G) X[c * ldx + r] -= sc[512 + c - jj];
+          a0 = tau != 0.0 ? 1.0 : 0.0;
           if (ug == 0) X[jj * ldx + r] = beta;
-        } else if (rg > j) {
-          double vr = xr0[q];
-          if (tau != 0.0) {
-            vr = xr0[q] / scale;
-            if (ug == 0) X[jj * ldx + r] = vr;
-            for (int c = jj + 1 + ug; c < ws; c += G) X[c * ldx + r] -= sc[512 + c - jj] * vr;
-          }
+        } else if (tau != 0.0) {
+          a0 = xr0[q] / scale;
+          if (ug == 0) X[jj * ldx + r] = a0;
           if (two) {
             if (rg == j + 1) {
-              for (int c = jj + 2 + ug; c < ws; c += G) X[c * ldx + r] -= sc[576 + c - jj];
-              if (ug == 0) X[(jj + 1) * ldx + r] = beta1;
+              a1 = 1.0;
             } else {
-              // column jj+1's entry after H_j (the same operation as the
-              // update of column jj+1 above), then its reflector's entry
+              // column jj+1's entry after H_j (the same operation as its
+              // update below), then its reflector's entry
               double y1r = xr1[q];
-              y1r -= sc[512 + 1] * vr;
-              const double vr1 = y1r / scale1;
-              if (ug == 0) X[(jj + 1) * ldx + r] = vr1;
-              for (int c = jj + 2 + ug; c < ws; c += G) X[c * ldx + r] -= sc[576 + c - jj] * vr1;
+              y1r -= sc[512 + 1] * a0;
+              a1 = y1r / scale1;
             }
           }
         }
+        // four columns at a time: loads first (clamped to the slab), then
+        // the updates, then the stores of the columns that exist
+        for (int c0 = jj + 1 + ug; c0 < ws; c0 += 4 * G) {
+          double xv[4], f0v[4], f1v[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = min(c0 + i * G, ws - 1);
+            xv[i] = X[c * ldx + r];
+            f0v[i] = sc[512 + c - jj];
+            f1v[i] = sc[576 + c - jj];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = c0 + i * G;
+            if (do0) xv[i] -= f0v[i] * a0;
+            if (do1 && c > jj + 1) xv[i] -= f1v[i] * a1;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = c0 + i * G;
+            if (c < ws) X[c * ldx + r] = xv[i];
+          }
+        }
+        // the second reflector's column: R entry on row j + 1, v_{j+1} below
+        if (do1 && ug == 0) X[(jj + 1) * ldx + r] = rg == j + 1 ? beta1 : a1;
       }
       __syncthreads();
       jj += two ? 2 : 1;
