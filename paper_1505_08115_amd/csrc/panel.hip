@@ -173,15 +173,18 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           beta = 0.0;
         }
       }
+      // v = (x - beta e_j) / scale is formed as a product with 1/scale (one
+      // division per thread instead of one per use)
+      const double rs = 1.0 / scale;
       // column jj+1 after H_j: y = H_j x_{j+1}; its norm over rows > j is
       // g1_{jj+1} - y(j)^2, taken only while the subtracted part is less
       // than half (relative error below 2 u); otherwise a step of its own
       int two = 0;
       double beta1 = 0.0, tau1 = 0.0, scale1 = 1.0, v0n = 0.0, yj = 0.0;
       if (pair && tau != 0.0) {
-        const double f01 = tau * ((sc[1] - beta * sc[W + 1]) / scale);
+        const double f01 = tau * ((sc[1] - beta * sc[W + 1]) * rs);
         yj = sc[W + 1] - f01;
-        v0n = sc[3 * W] / scale;                      // v_j(j+1)
+        v0n = sc[3 * W] * rs;                         // v_j(j+1)
         const double y1 = sc[3 * W + 1] - f01 * v0n;  // y(j+1)
         const double g11 = sc[2 * W + 1];
         const double n1 = g11 - yj * yj;
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           scale1 = y1 - beta1;
         }
       }
+      const double rs1 = 1.0 / scale1;
       if (t == 0) {
         if (!(nrm2 == nrm2) || nrm2 > 1.79e308) flag_nonfinite(p.info, p.block_index);
         taus[jj] = tau;
@@ -204,12 +208,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       // f0_c = tau v_j^T x_c at sc[512 + c - jj]; with a pair, f1_c =
       // tau1 v_{j+1}^T (H_j x_c) at sc[576 + c - jj] for c > jj + 1
       if (t > 0 && t < E) {
-        const double f0 = tau * ((sc[t] - beta * sc[W + t]) / scale);
+        const double f0 = tau * ((sc[t] - beta * sc[W + t]) * rs);
         sc[512 + t] = f0;
         if (two && t > 1) {
           const double zj = sc[W + t] - f0, zj1 = sc[3 * W + t] - f0 * v0n;
           const double yz = sc[2 * W + t] - yj * zj;   // y^T z over rows > j
-          sc[576 + t] = tau1 * ((yz - beta1 * zj1) / scale1);
+          sc[576 + t] = tau1 * ((yz - beta1 * zj1) * rs1);
         }
       }
       // Row updates: G threads per row (G = 1 when a workgroup has more than
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           a0 = tau != 0.0 ? 1.0 : 0.0;
           if (ug == 0) X[jj * ldx + r] = beta;
         } else if (tau != 0.0) {
-          a0 = xr0[q] / scale;
+          a0 = xr0[q] * rs;
           if (ug == 0) X[jj * ldx + r] = a0;
           if (two) {
             if (rg == j + 1) {
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
               // update below), then its reflector's entry
               double y1r = xr1[q];
               y1r -= sc[512 + 1] * a0;
-              a1 = y1r / scale1;
+              a1 = y1r * rs1;
             }
           }
         }

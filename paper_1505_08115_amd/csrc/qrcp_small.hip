@@ -368,10 +368,11 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
           tau = (beta - a) / beta;
           scale = a - beta;
         }
+        const double rs = 1.0 / scale;   // one division; v = x / scale as products
 #pragma unroll
         for (int u = 0; u < kRMaxRows / 64; ++u) {
           const int r = j + lane + 64 * u;
-          if (r < k) v[r] = (r == j) ? 1.0 : (tau != 0.0 ? xs[u] / scale : xs[u]);
+          if (r < k) v[r] = (r == j) ? 1.0 : (tau != 0.0 ? xs[u] * rs : xs[u]);
         }
         // rows < j of v stay zero, so the column updates need no row masks
         if (lane == 0 && j > 0) v[j - 1] = 0.0;
