@@ -443,7 +443,9 @@ void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   const int64_t tiles = (g.N + kRowsBN - 1) / kRowsBN;
   const int64_t slots = g.max_wg > 0 ? std::min<int64_t>(g.max_wg, kRowsSlots) : kRowsSlots;
   int64_t sp = slots / tiles;                                // tiles * splits <= one round
-  const int64_t maxsp = g.K / (kBK * 16);                    // at least 256 of K per split
+  // at least 64 of K per split: short products (the late blocks' W = V^T C,
+  // a few 128-column slabs) then still spread over most of the CUs
+  const int64_t maxsp = g.K / (kBK * 4);
   if (sp > maxsp) sp = maxsp;
   if (sp > 64) sp = 64;
   if (sp < 1) sp = 1;
