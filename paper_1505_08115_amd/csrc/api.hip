@@ -100,6 +100,7 @@ struct FactorPlan {
   // overlapped schedule (FP64 storage, permutation pivots, sampled blocks)
   bool pipe = false;
   size_t GVb = 0, gpart_aux = 0;
+  size_t vtpart = 0;   // split-K buffer of V T^T (on the side stream, beside W)
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -139,7 +140,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
   if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
 
-  size_t Yd = 0, gpart = 0, ppart = 0, gpart32 = 0, spart = 0;
+  size_t Yd = 0, gpart = 0, ppart = 0, gpart32 = 0, spart = 0, vtp = 0;
   int qnwg = 0;
   int64_t qk = 1;
   for (int64_t i = 0; i < P.nblocks; ++i) {
@@ -148,6 +149,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     const int pn = panel_config(mi, (int)bi, &rpw);
     if (pn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "panel too large for the panel kernel");
     ppart = std::max(ppart, panel_part_doubles(pn, (int)bi));
+    vtp = std::max(vtp, gemm_part_doubles(mi, bi, bi));
     if (!P.fixed) {
       if (block_is_classical_tail(P, i)) {
         int cpw = 0;
@@ -231,6 +233,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Acopy = w.take(P.fixed ? (size_t)m * n * es : 0);
   P.GVb = w.take(P.pipe ? (size_t)P.ks * P.b * d : 0);
   P.gpart_aux = w.take(gpaux * d);
+  P.vtpart = w.take(vtp * d);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -488,6 +491,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   float *VS32 = at<float>(work, P.VS32), *TS32 = at<float>(work, P.TS32);
   void *Gb = at<void>(work, P.Gb);
   double *GVb = at<double>(work, P.GVb), *gpart_aux = at<double>(work, P.gpart_aux);
+  double *vtpart = at<double>(work, P.vtpart);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -706,6 +710,13 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
         CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
       }
+      {
+        // V T^T right after T, also beside W (its own split-K buffer)
+        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi), h->side);
+        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
+        CHK(launch_gemm_f64(h->side, gv, vtpart), "V T^T");
+        if constexpr (F32) CHK(launch_copy_f64_f32(h->side, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
+      }
       CHK(hipEventRecord(h->join_ev, h->side), "join event");
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
@@ -720,13 +731,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
       }
-      CHK(hipStreamWaitEvent(s, h->join_ev, 0), "join T");
-      {
-        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi));
-        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
-        CHK(launch_gemm_f64(s, gv, gpart), "V T^T");
-        if constexpr (F32) CHK(launch_copy_f64_f32(s, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
-      }
+      CHK(hipStreamWaitEvent(s, h->join_ev, 0), "join T and V T^T");
       if (pipe_next) {
         if constexpr (!F32) {
           // the update on the auxiliary stream, the next sketch's correction here
