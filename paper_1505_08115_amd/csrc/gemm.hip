@@ -491,6 +491,9 @@ hipError_t launch_rows(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchu
   const int mt = (int)((g.M + 15) / 16);
   if (mt <= 8) return launch_rows_mt<T, 8, TA>(s, g, splits, kchunk, partial);
   if (mt <= 12) return launch_rows_mt<T, 12, TA>(s, g, splits, kchunk, partial);
+  // M = 256 (W = V^T C at b = 256) gets its own instance: under MT = 18 two of
+  // the 18 row blocks would be padding, an eighth of the MFMAs
+  if (mt <= 16) return launch_rows_mt<T, 16, TA>(s, g, splits, kchunk, partial);
   if (mt <= 18 || rows_max_mt<T>() <= 18) return launch_rows_mt<T, 18, TA>(s, g, splits, kchunk, partial);
   if constexpr (rows_max_mt<T>() > 18) {
     if (mt <= 24) return launch_rows_mt<T, 24, TA>(s, g, splits, kchunk, partial);
