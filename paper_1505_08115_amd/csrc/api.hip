@@ -101,6 +101,7 @@ struct FactorPlan {
   bool pipe = false;
   size_t GVb = 0, gpart_aux = 0;
   size_t vtpart = 0;   // split-K buffer of V T^T (on the side stream, beside W)
+  size_t W2 = 0;       // T^T W (overlapped schedule)
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -202,8 +203,10 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
       if (block_is_classical_tail(P, i + 1) || ni <= bi) continue;
       gpaux = std::max(gpaux, gemm_part_doubles(P.ks, ni - bi, mi - bi));
       gpaux = std::max(gpaux, gemm_part_doubles(mi, ni - bi, bi));
+      gpaux = std::max(gpaux, gemm_part_doubles(P.ks, bi, mi - bi));   // G V
       gpart = std::max(gpart, gemm_part_doubles(P.ks, bi, mi - bi));
       gpart = std::max(gpart, gemm_part_doubles(P.ks, ni - bi, bi));
+      gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));     // T^T W
     }
   P.Y_doubles = Yd;
   P.nslots = (int)(3 * P.nblocks + 4);
@@ -234,6 +237,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.GVb = w.take(P.pipe ? (size_t)P.ks * P.b * d : 0);
   P.gpart_aux = w.take(gpaux * d);
   P.vtpart = w.take(vtp * d);
+  P.W2 = w.take(P.pipe ? (size_t)P.b * n * d : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -492,6 +496,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   void *Gb = at<void>(work, P.Gb);
   double *GVb = at<double>(work, P.GVb), *gpart_aux = at<double>(work, P.gpart_aux);
   double *vtpart = at<double>(work, P.vtpart);
+  double *W2 = at<double>(work, P.W2);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -656,7 +661,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     // panel (64) or the pivoted QR (at most 128) room plus slack for the
     // main stream's short kernels (granting the products exactly what the
     // persistent kernel leaves free measured 12 % slower overall)
-    const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2;
+    const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2, beside_w = h->ncu / 4;
     if constexpr (!F32) if (pipe_next) {
       CHK(hipEventRecord(h->ev_moves, s), "fork event");
       CHK(hipStreamWaitEvent(aux, h->ev_moves, 0), "auxiliary stream wait");
@@ -674,7 +679,6 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         gy.max_wg = beside_panel;
         CHK(launch_gemm_f64(aux, gy, gpart_aux), "sketch product of the next block");
       }
-      CHK(hipEventRecord(h->ev_ypre, aux), "sketch product event");
     }
     // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi) in FP64
     {
@@ -704,13 +708,18 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       // workgroup per block row would leave most of the chip idle).
       T *C = X + bi * lda;
       const double nc = (double)(ni - bi);
+      // Overlapped FP64 blocks reassociate the update as C - V (T^T W): the
+      // correction of the next sketch is then (G V(b_i:, :)) (T^T W), whose
+      // first factor needs only V and runs on the auxiliary stream beside W,
+      // and no V T^T is formed
+      const bool reassoc = !F32 && pipe_next;
       CHK(hipEventRecord(h->fork_ev, s), "fork event");
       CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
       {
         ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
         CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
       }
-      {
+      if (!reassoc) {
         // V T^T right after T, also beside W (its own split-K buffer)
         ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi), h->side);
         GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
@@ -718,6 +727,17 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         if constexpr (F32) CHK(launch_copy_f64_f32(h->side, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
       }
       CHK(hipEventRecord(h->join_ev, h->side), "join event");
+      if constexpr (!F32)
+        if (reassoc) {
+          // G_{i+1} V(b_i:, :) on the auxiliary stream after the sketch product
+          CHK(hipStreamWaitEvent(aux, h->fork_ev, 0), "auxiliary stream wait for V");
+          const int64_t mn = mi - bi;
+          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * mn, 8.0 * (ks * mn + mn * bi + ks * bi), aux);
+          GemmF64 g1{false, false, ks, bi, mn, Gn, ks, Vb + bi, mi, GVb, ks, 1.0, 0.0};
+          g1.max_wg = beside_w;
+          CHK(launch_gemm_f64(aux, g1, gpart_aux), "G V");
+          CHK(hipEventRecord(h->ev_ypre, aux), "correction factor event");
+        }
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
@@ -731,28 +751,30 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
       }
-      CHK(hipStreamWaitEvent(s, h->join_ev, 0), "join T and V T^T");
+      CHK(hipStreamWaitEvent(s, h->join_ev, 0), reassoc ? "join T" : "join T and V T^T");
       if (pipe_next) {
         if constexpr (!F32) {
+          {
+            ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * bi * bi * nc, 8.0 * (bi * bi + 2.0 * bi * nc));
+            GemmF64 gw2{true, false, bi, ni - bi, bi, Ti, b, Wb, bi, W2, bi, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, gw2, gpart), "T^T W");
+          }
           // the update on the auxiliary stream, the next sketch's correction here
           CHK(hipEventRecord(h->ev_vt, s), "update fork event");
           CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
           {
             ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
                            (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
-            GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0, true};
+            GemmF64 gu{false, false, mi, ni - bi, bi, Vb, mi, W2, bi, C, lda, -1.0, 1.0, true};
             gu.max_wg = beside_qrcp;
-            CHK(launch_gemm_f64(aux, gu, gpart_aux), "C -= (V T^T) W");
+            CHK(launch_gemm_f64(aux, gu, gpart_aux), "C -= V (T^T W)");
           }
           CHK(hipEventRecord(h->ev_upd, aux), "update event");
           upd_pending = true;
-          CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product");
-          const int64_t mn = mi - bi;
-          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * (mn + nc), 8.0 * (ks * mn + 2.0 * ks * nc + bi * nc));
-          GemmF64 g1{false, false, ks, bi, mn, Gn, ks, Vt + bi, mi, GVb, ks, 1.0, 0.0};
-          CHK(launch_gemm_f64(s, g1, gpart), "G (V T^T)");
-          GemmF64 g2{false, false, ks, ni - bi, bi, GVb, ks, Wb, bi, Y, ks, -1.0, 1.0};
-          CHK(launch_gemm_f64(s, g2, gpart), "Y -= (G V T^T) W");
+          CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product and G V");
+          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * nc, 8.0 * (ks * bi + 2.0 * ks * nc + bi * nc));
+          GemmF64 g2{false, false, ks, ni - bi, bi, GVb, ks, W2, bi, Y, ks, -1.0, 1.0};
+          CHK(launch_gemm_f64(s, g2, gpart), "Y -= (G V) (T^T W)");
           y_ready = true;
         }
       } else {

@@ -11,6 +11,9 @@
 //  * 256 threads = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
 //    block of 16 x 16 MFMA tiles; K advances by BK = 16 through two LDS
 //    stages, the next K slab is prefetched into registers during the MFMAs.
+//    The grid-capped FP64 trailing update uses 256 x 128 tiles by 512
+//    threads (8 waves in 4 x 2, the same 64 x 64 block per wave), so that
+//    one workgroup per CU still has two waves per SIMD.
 //  * Global loads are flattened so that consecutive lanes read consecutive
 //    addresses along the contiguous dimension of each operand.
 //  * Split-K: when the M x N tile grid is too small to fill 256 CUs, K is cut
