@@ -433,7 +433,7 @@ constexpr int rows_max_mt() { return sizeof(T) == 8 ? 18 : 28; }   // FP64 accum
 
 template <typename T>
 bool use_rows(const Gemm<T> &g) {
-  return !g.ta && !g.tb && g.M > 64 && g.M <= 16 * rows_max_mt<T>() && g.K >= 1024 && g.N >= 256;
+  return !g.ta && !g.tb && g.M > 64 && g.M <= 16 * rows_max_mt<T>() && g.K >= 256 && g.N >= 256;
 }
 
 // One workgroup per CU (its LDS stages take most of the CU's 160 KiB), so the
