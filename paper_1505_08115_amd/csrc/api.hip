@@ -188,6 +188,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     if (ni > bi) {
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, mi));
       gpart = std::max(gpart, gemm_part_doubles(mi, ni - bi, bi));
+      gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));   // T^T W
       gpart32 = std::max(gpart32, gemm_part_doubles(bi, ni - bi, mi));
       gpart32 = std::max(gpart32, gemm_part_doubles(mi, ni - bi, bi));
     }
@@ -237,7 +238,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.GVb = w.take(P.pipe ? (size_t)P.ks * P.b * d : 0);
   P.gpart_aux = w.take(gpaux * d);
   P.vtpart = w.take(vtp * d);
-  P.W2 = w.take(P.pipe ? (size_t)P.b * n * d : 0);
+  P.W2 = w.take(P.f32 ? 0 : (size_t)P.b * n * d);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -708,11 +709,12 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       // workgroup per block row would leave most of the chip idle).
       T *C = X + bi * lda;
       const double nc = (double)(ni - bi);
-      // Overlapped FP64 blocks reassociate the update as C - V (T^T W): the
-      // correction of the next sketch is then (G V(b_i:, :)) (T^T W), whose
-      // first factor needs only V and runs on the auxiliary stream beside W,
-      // and no V T^T is formed
-      const bool reassoc = !F32 && pipe_next;
+      // FP64 applies the update as C - V (T^T W) (every block, so that a
+      // fixed-pivot refactorization repeats the forward's operations): in the
+      // overlapped schedule the correction of the next sketch is then
+      // (G V(b_i:, :)) (T^T W), whose first factor needs only V and runs on
+      // the auxiliary stream beside W; no V T^T is formed
+      const bool reassoc = !F32;
       CHK(hipEventRecord(h->fork_ev, s), "fork event");
       CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
       {
@@ -728,7 +730,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       }
       CHK(hipEventRecord(h->join_ev, h->side), "join event");
       if constexpr (!F32)
-        if (reassoc) {
+        if (pipe_next) {
           // G_{i+1} V(b_i:, :) on the auxiliary stream after the sketch product
           CHK(hipStreamWaitEvent(aux, h->fork_ev, 0), "auxiliary stream wait for V");
           const int64_t mn = mi - bi;
@@ -752,13 +754,13 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         }
       }
       CHK(hipStreamWaitEvent(s, h->join_ev, 0), reassoc ? "join T" : "join T and V T^T");
+      if constexpr (!F32) {
+        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * bi * bi * nc, 8.0 * (bi * bi + 2.0 * bi * nc));
+        GemmF64 gw2{true, false, bi, ni - bi, bi, Ti, b, Wb, bi, W2, bi, 1.0, 0.0};
+        CHK(launch_gemm_f64(s, gw2, gpart), "T^T W");
+      }
       if (pipe_next) {
         if constexpr (!F32) {
-          {
-            ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * bi * bi * nc, 8.0 * (bi * bi + 2.0 * bi * nc));
-            GemmF64 gw2{true, false, bi, ni - bi, bi, Ti, b, Wb, bi, W2, bi, 1.0, 0.0};
-            CHK(launch_gemm_f64(s, gw2, gpart), "T^T W");
-          }
           // the update on the auxiliary stream, the next sketch's correction here
           CHK(hipEventRecord(h->ev_vt, s), "update fork event");
           CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
@@ -781,8 +783,8 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
                        (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
-          GemmF64 gu{false, false, mi, ni - bi, bi, Vt, mi, Wb, bi, C, lda, -1.0, 1.0, true};
-          CHK(launch_gemm_f64(s, gu, gpart), "C -= (V T^T) W");
+          GemmF64 gu{false, false, mi, ni - bi, bi, Vb, mi, W2, bi, C, lda, -1.0, 1.0, true};
+          CHK(launch_gemm_f64(s, gu, gpart), "C -= V (T^T W)");
         } else {
           GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
           CHK(launch_gemm<float>(s, gu, gpart32), "C -= (V T^T) W");
