@@ -221,9 +221,9 @@ typedef enum {
   RQRCP_K_MOVES = 3,       /* moving the pivot columns (all m rows)           */
   RQRCP_K_PANEL = 4,       /* unpivoted Householder QR of the panel           */
   RQRCP_K_TFACTOR = 5,     /* T of the compact WY form                        */
-  RQRCP_K_VT_GEMM = 6,     /* V T^T                                           */
+  RQRCP_K_VT_GEMM = 6,     /* T^T W (FP64), V T^T (FP32 storage)              */
   RQRCP_K_W_GEMM = 7,      /* W = V^T C                                       */
-  RQRCP_K_UPDATE_GEMM = 8, /* C -= (V T^T) W                                  */
+  RQRCP_K_UPDATE_GEMM = 8, /* C -= V (T^T W) (FP64), (V T^T) W (FP32)         */
   RQRCP_K_ORTHO = 9,       /* QR of the sketch and right-application of S_i   */
   RQRCP_K_OTHER = 10,
   RQRCP_K_COUNT = 11
@@ -231,6 +231,11 @@ typedef enum {
 rqrcp_status_t rqrcp_timing_enable(rqrcp_handle_t h, int enable);
 rqrcp_status_t rqrcp_timing_read(rqrcp_handle_t h, int kclass, int64_t *launches, double *ms, double *flops,
                                  double *bytes);
+/* Restrict the timing to the classes whose bit is set in mask (bit k = class
+ * k; the default, and any mask with all bits set, times every class), so that
+ * a measurement can bracket one class without the events of the others.
+ * Errors: RQRCP_ERR_ARG for a NULL handle. */
+rqrcp_status_t rqrcp_timing_classes(rqrcp_handle_t h, uint32_t mask);
 
 #ifdef __cplusplus
 }

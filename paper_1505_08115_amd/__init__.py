@@ -32,7 +32,7 @@ EXPORTS = [
     "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
     "rqrcp_apply_p_work_bytes", "rqrcp_apply_p", "rqrcp_lowrank_work_bytes", "rqrcp_lowrank",
     "rqrcp_lowrank_backward_work_bytes", "rqrcp_lowrank_backward", "rqrcp_sketch", "rqrcp_timing_enable",
-    "rqrcp_timing_read",
+    "rqrcp_timing_read", "rqrcp_timing_classes",
 ]
 
 #: kernel classes of rqrcp_timing_read
@@ -90,6 +90,7 @@ def load_library():
                                           _vp, _i64, _vp, _i64, _vp, _sz]),
         "rqrcp_sketch": (_i32, [_vp, _u64, _i64, _i64, _i64, _i64, _vp, _i64]),
         "rqrcp_timing_enable": (_i32, [_vp, _i32]),
+        "rqrcp_timing_classes": (_i32, [_vp, ctypes.c_uint32]),
         "rqrcp_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     }
@@ -299,6 +300,13 @@ def timing_enable(enable=True, device=None):
     """Bracket every kernel class's launches with HIP events (no host sync)."""
     h = handle(device)
     _check(load_library().rqrcp_timing_enable(h, 1 if enable else 0), h)
+
+
+def timing_classes(classes=None, device=None):
+    """Bracket only the named kernel classes while timing is on (None: all)."""
+    h = handle(device)
+    mask = 0xFFFFFFFF if classes is None else sum(1 << KERNEL_CLASSES.index(c) for c in classes)
+    _check(load_library().rqrcp_timing_classes(h, mask), h)
 
 
 def timing_read(device=None):

@@ -28,11 +28,12 @@ struct rqrcp_ctx {
   // kernels beside them find their CUs free.
   hipStream_t aux = nullptr;
   int ncu = 0;
-  hipEvent_t ev_moves = nullptr, ev_ypre = nullptr, ev_vt = nullptr, ev_upd = nullptr;
+  hipEvent_t ev_moves = nullptr, ev_ypre = nullptr, ev_vt = nullptr, ev_upd = nullptr, ev_w = nullptr;
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
   bool timing = false;
+  uint32_t timing_mask = 0xFFFFFFFFu;   // classes bracketed while timing is on
   std::vector<hipEvent_t> free_events;
   std::vector<hipEvent_t> all_events;
   std::vector<rqrcp_timing_rec> recs;
@@ -285,7 +286,7 @@ struct ScopedTimer {
   hipStream_t stream;
   ScopedTimer(rqrcp_handle_t hh, int kc, double f, double b, hipStream_t st = nullptr)
       : h(hh), kclass(kc), flops(f), bytes(b), stream(st ? st : hh->stream) {
-    if (h->timing) {
+    if (h->timing && ((h->timing_mask >> kc) & 1u)) {
       start = take_event(h);
       if (start) (void)hipEventRecord(start, stream);
     }
@@ -358,7 +359,7 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-  hipEvent_t *evs[4] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd};
+  hipEvent_t *evs[5] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd, &c->ev_w};
   for (hipEvent_t *ev : evs)
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -391,7 +392,7 @@ rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
   for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
-  for (hipEvent_t e : {h->ev_moves, h->ev_ypre, h->ev_vt, h->ev_upd})
+  for (hipEvent_t e : {h->ev_moves, h->ev_ypre, h->ev_vt, h->ev_upd, h->ev_w})
     if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -402,6 +403,12 @@ rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
 rqrcp_status_t rqrcp_timing_enable(rqrcp_handle_t h, int enable) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   h->timing = enable != 0;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_timing_classes(rqrcp_handle_t h, uint32_t mask) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  h->timing_mask = mask;
   return RQRCP_OK;
 }
 
@@ -662,7 +669,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     // panel (64) or the pivoted QR (at most 128) room plus slack for the
     // main stream's short kernels (granting the products exactly what the
     // persistent kernel leaves free measured 12 % slower overall)
-    const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2, beside_w = h->ncu / 4;
+    const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2;
     if constexpr (!F32) if (pipe_next) {
       CHK(hipEventRecord(h->ev_moves, s), "fork event");
       CHK(hipStreamWaitEvent(aux, h->ev_moves, 0), "auxiliary stream wait");
@@ -729,17 +736,6 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         if constexpr (F32) CHK(launch_copy_f64_f32(h->side, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
       }
       CHK(hipEventRecord(h->join_ev, h->side), "join event");
-      if constexpr (!F32)
-        if (pipe_next) {
-          // G_{i+1} V(b_i:, :) on the auxiliary stream after the sketch product
-          CHK(hipStreamWaitEvent(aux, h->fork_ev, 0), "auxiliary stream wait for V");
-          const int64_t mn = mi - bi;
-          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * mn, 8.0 * (ks * mn + mn * bi + ks * bi), aux);
-          GemmF64 g1{false, false, ks, bi, mn, Gn, ks, Vb + bi, mi, GVb, ks, 1.0, 0.0};
-          g1.max_wg = beside_w;
-          CHK(launch_gemm_f64(aux, g1, gpart_aux), "G V");
-          CHK(hipEventRecord(h->ev_ypre, aux), "correction factor event");
-        }
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
@@ -753,6 +749,19 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
       }
+      if constexpr (!F32)
+        if (pipe_next) {
+          // G_{i+1} V(b_i:, :) on the auxiliary stream after W (beside T^T W;
+          // beside W itself it slowed W by a sixth)
+          CHK(hipEventRecord(h->ev_w, s), "W event");
+          CHK(hipStreamWaitEvent(aux, h->ev_w, 0), "auxiliary stream wait for W");
+          const int64_t mn = mi - bi;
+          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * mn, 8.0 * (ks * mn + mn * bi + ks * bi), aux);
+          GemmF64 g1{false, false, ks, bi, mn, Gn, ks, Vb + bi, mi, GVb, ks, 1.0, 0.0};
+          g1.max_wg = beside_qrcp;
+          CHK(launch_gemm_f64(aux, g1, gpart_aux), "G V");
+          CHK(hipEventRecord(h->ev_ypre, aux), "correction factor event");
+        }
       CHK(hipStreamWaitEvent(s, h->join_ev, 0), reassoc ? "join T" : "join T and V T^T");
       if constexpr (!F32) {
         ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * bi * bi * nc, 8.0 * (bi * bi + 2.0 * bi * nc));
