@@ -495,7 +495,7 @@ size_t lds_doubles(int k, int cpw) {
 
 static int rpl_for(int k) {
   const int r = (k + kRLanes - 1) / kRLanes;
-  return ((r + 3) / 4) * 4;   // rows per lane rounded up to a multiple of 4
+  return ((r + 1) / 2) * 2;   // rows per lane rounded up to a multiple of 2 (two norm chains)
 }
 
 int qrcp_small_config(int k, int ncols, int *cpw) {
@@ -538,19 +538,14 @@ hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
   if (nwg == 0) return hipErrorInvalidValue;
   if (q.k <= kRMaxRows) {
     switch (rpl_for(q.k)) {
-      case 4: return launch_reg<4>(s, nwg, q);
-      case 8: return launch_reg<8>(s, nwg, q);
-      case 12: return launch_reg<12>(s, nwg, q);
-      case 16: return launch_reg<16>(s, nwg, q);
-      case 20: return launch_reg<20>(s, nwg, q);
-      case 24: return launch_reg<24>(s, nwg, q);
-      case 28: return launch_reg<28>(s, nwg, q);
-      case 32: return launch_reg<32>(s, nwg, q);
-      case 36: return launch_reg<36>(s, nwg, q);
-      case 40: return launch_reg<40>(s, nwg, q);
-      case 44: return launch_reg<44>(s, nwg, q);
-      case 48: return launch_reg<48>(s, nwg, q);
-      case 52: return launch_reg<52>(s, nwg, q);
+#define RQ_REG_CASE(r) \
+  case r: return launch_reg<r>(s, nwg, q);
+      RQ_REG_CASE(2) RQ_REG_CASE(4) RQ_REG_CASE(6) RQ_REG_CASE(8) RQ_REG_CASE(10) RQ_REG_CASE(12) RQ_REG_CASE(14)
+      RQ_REG_CASE(16) RQ_REG_CASE(18) RQ_REG_CASE(20) RQ_REG_CASE(22) RQ_REG_CASE(24) RQ_REG_CASE(26)
+      RQ_REG_CASE(28) RQ_REG_CASE(30) RQ_REG_CASE(32) RQ_REG_CASE(34) RQ_REG_CASE(36) RQ_REG_CASE(38)
+      RQ_REG_CASE(40) RQ_REG_CASE(42) RQ_REG_CASE(44) RQ_REG_CASE(46) RQ_REG_CASE(48) RQ_REG_CASE(50)
+      RQ_REG_CASE(52) RQ_REG_CASE(54)
+#undef RQ_REG_CASE
       default: return launch_reg<56>(s, nwg, q);
     }
   }
