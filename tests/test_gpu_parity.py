@@ -480,3 +480,40 @@ def test_panel_pairs_fallbacks_and_zero_columns():
     assert np.max(np.abs(Rg - Ro)) <= 1e-8 * nA
     taus = Fz.tau.cpu().numpy()
     assert taus[9] == 0.0 and Rg[9, 9] == 0.0
+
+
+@pytest.mark.parametrize("m,n,b", [(640, 512, 64), (1024, 1024, 128)])
+def test_fixed_pivot_refactorization_repeats_the_forward(m, n, b):
+    """The forward (overlapped schedule: next sketch and update on the
+    auxiliary stream) and a fixed-pivot refactorization (serial schedule, no
+    sketch) apply the same operations to the panel and trailing columns, so
+    R, the reflectors, tau and T agree bit for bit."""
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 6.0), seed=m + b).to(DEV)
+    Fz = R.factor(A, block=b, oversample=8, seed=4)
+    Fx = R.factor(A, block=b, oversample=8, seed=4, jpvt=Fz.jpvt)
+    torch.cuda.synchronize()
+    assert torch.equal(Fx.jpvt, Fz.jpvt)
+    assert torch.equal(Fx.F, Fz.F)
+    assert torch.equal(Fx.tau, Fz.tau)
+    assert torch.equal(Fx.T, Fz.T)
+
+
+def test_timing_classes_restrict_the_bracketed_launches():
+    A = R.colmajor(torch.randn(512, 384, dtype=torch.float64, device=DEV))
+    R.timing_classes(["w_gemm"])
+    R.timing_enable(True)
+    R.timing_read()
+    try:
+        R.factor(A, block=64, oversample=8, seed=2)
+        torch.cuda.synchronize()
+        only_w = R.timing_read()
+        R.timing_classes(None)
+        R.factor(A, block=64, oversample=8, seed=2)
+        torch.cuda.synchronize()
+        every = R.timing_read()
+    finally:
+        R.timing_enable(False)
+        R.timing_classes(None)
+    assert set(only_w) == {"w_gemm"} and only_w["w_gemm"][0] == 384 // 64 - 1
+    assert {"w_gemm", "panel", "qrcp", "update_gemm"} <= set(every)
+    assert every["w_gemm"][0] == only_w["w_gemm"][0]
