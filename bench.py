@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-residual", action="store_true", help="skip the residual check (profiling)")
     ap.add_argument("--cpu-blocks", type=int, default=2, help="oracle sample: leading blocks factored on the CPU")
     ap.add_argument("--no-bwd", action="store_true", help="skip the bwd/fwd ratio measurement (C5)")
+    ap.add_argument("--power", type=int, default=1,
+                    help="also time the workload with this many power-iteration steps (Section 6.3); 0 skips")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain copy-like kernel (torch.neg) over 2^26 doubles, to scale HBM counters")
     return ap.parse_args()
@@ -170,7 +172,7 @@ def main():
     A = W.workload_matrix(w, device=dev)
     m, n = A.shape
 
-    def run(wl, Ain, steps, warmup, profile, check=True):
+    def run(wl, Ain, steps, warmup, profile, check=True, power=0):
         """Time `steps` factorizations of Ain (already resident) with HIP events.
 
         Inside the timed steps only the W = V^T C and trailing-update launches
@@ -182,7 +184,7 @@ def main():
         A0 = R.colmajor(Ain.to(dtype))
         F = torch.empty_like(A0)
         sizes = R.factor_sizes(m, n, dtype, block=wl.b, oversample=wl.p, pivot=wl.pivot, rank=wl.rank,
-                               precision="mixed" if wl.precision == "mixed" else "plain")
+                               precision="mixed" if wl.precision == "mixed" else "plain", power=power)
         jp = torch.empty(n, dtype=torch.int32, device=dev)
         tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
         T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
@@ -190,7 +192,7 @@ def main():
         work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
         info = torch.zeros(4, dtype=torch.int32, device=dev)
         kw = dict(block=wl.b, oversample=wl.p, seed=wl.seed, pivot=wl.pivot, rank=wl.rank, info=info,
-                  precision="mixed" if wl.precision == "mixed" else "plain")
+                  precision="mixed" if wl.precision == "mixed" else "plain", power=power)
         for _ in range(warmup):
             F.copy_(A0)
             R.factor_into(F, jp, tau, T, S, work, **kw)
@@ -250,6 +252,18 @@ def main():
                  "speedup_vs_fp64": ms / mms,
                  "breakdown": {k: v[1] / args.steps for k, v in mprof.items()}}
 
+    # the same factorization with q steps of the power iteration on every
+    # sketch (Section 6.3): two more products per block, serial schedule
+    power = None
+    if args.power > 0 and w.precision != "mixed":
+        pt, (_, pprof), pres, pinfo = run(w, A, args.steps, args.warmup, True, check=not args.no_residual,
+                                          power=args.power)
+        pms = float(np.mean(pt))
+        power = {"workload": f"{w.name} with q={args.power} power-iteration steps per sketch",
+                 "ms_per_step": pms, "value": flops / (pms * 1e-3) / 1e9, "slowdown_vs_q0": pms / ms,
+                 "residual": pres, "info": pinfo,
+                 "breakdown": {k: v[1] / args.steps for k, v in pprof.items()}}
+
     # roofline of the dominant matrix-core kernel on the critical path: W = V^T C
     # (the sketch product and the trailing update run on the capped auxiliary
     # stream, overlapped with the panel and the pivoted QR; reported below)
@@ -286,7 +300,7 @@ def main():
         "roofline": roof,
         "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "latency": latency,
                   "update_overlapped": update_overlapped,
-                  "mixed": mixed},
+                  "mixed": mixed, "power_iteration": power},
     }
     if not args.no_bwd:
         out["extra"]["bwd_fwd"] = bwd_fwd_ratio()

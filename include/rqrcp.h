@@ -93,6 +93,11 @@ typedef struct {
                         /* [0] = 1 if a non-finite norm was met, [1] = first block     */
                         /* where that happened (+1), [2] = 1 if a grid-wide wait gave  */
                         /* up (results invalid), [3] reserved                          */
+  int32_t power;        /* q in [0, 8]: steps of the power iteration of Section 6.3 on */
+                        /* every sketched block, Y_i = G_i X_i (X_i^T X_i)^q; q > 0    */
+                        /* needs FP64 storage (else RQRCP_ERR_UNSUPPORTED), turns the  */
+                        /* overlapped schedule off and takes (b+p) m more doubles of   */
+                        /* workspace; ignored with fixed_pivots                        */
 } rqrcp_opts_t;
 
 /* Default options: b = 128, p = 10, full rank, permutation, plain, classical

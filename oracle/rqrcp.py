@@ -190,7 +190,7 @@ def sketch(seed, block, nsample, row0, nrows):
 
 
 def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
-          sampler="gaussian", trace=False):
+          sampler="gaussian", trace=False, power=0):
     """Blocked randomized QR (Fig. 3) of a copy of A; returns a dict.
 
     pivot   : "perm" (Section 4.1) or "ortho" (Section 4.2)
@@ -199,6 +199,8 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
     G       : optional list of per-block sketches G_i ((b+p) x (m-r0));
               None draws them from the counter-based generator
     sampler : "gaussian", or "identity" (Y_i := X_i; test reduction only)
+    power   : q >= 0 steps of the power iteration of Section 6.3 on each
+              sketched block: Y_i := G_i X_i (X_i^T X_i)^q
 
     Output keys: F (R on and above the diagonal, Householder vectors below),
     tau, T (list of per-block T), jpvt, S (list of (V_S, tau_S, T_S) per block
@@ -249,6 +251,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         else:
             Gi = G[i] if G is not None else sketch(seed, i, b + p, r0, mi)
             Y = Gi @ X
+            # Section 6.3, in the row form of the sample: each step multiplies
+            # by X_i^T X_i, as (Y X_i^T) X_i, with no re-orthonormalisation
+            for _ in range(int(power)):
+                Y = (Y @ X.T) @ X
         if trace:
             out["Y"].append(Y.copy())
         if pivot == "perm":

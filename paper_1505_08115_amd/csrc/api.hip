@@ -91,6 +91,7 @@ size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
 struct FactorPlan {
   int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
   bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
+  int power = 0;   // steps of the power iteration on every sketched block
   // FP32-storage buffers
   size_t Pw = 0, V32 = 0, VT32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
   int nslots = 0;
@@ -103,6 +104,7 @@ struct FactorPlan {
   size_t GVb = 0, gpart_aux = 0;
   size_t vtpart = 0;   // split-K buffer of V T^T (on the side stream, beside W)
   size_t W2 = 0;       // T^T W (overlapped schedule)
+  size_t Z = 0;        // Y X^T of the power iteration
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -129,6 +131,9 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->fixed_pivots != 0 && o->fixed_pivots != 1) return fail(h, RQRCP_ERR_ARG, "opts.fixed_pivots must be 0 or 1");
   if (o->fixed_pivots && o->pivot == RQRCP_PIVOT_ORTHO)
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.fixed_pivots applies to the permutation form only");
+  if (o->power < 0 || o->power > 8) return fail(h, RQRCP_ERR_ARG, "opts.power must be in [0, 8]");
+  if (o->power > 0 && dt != RQRCP_F64 && !o->fixed_pivots)
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only in this build");
   FactorPlan P;
   P.f32 = dt == RQRCP_F32;
   P.mixed = o->precision == RQRCP_PREC_MIXED;
@@ -138,6 +143,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.nblocks = cdiv(P.k, P.b);
   P.ortho = o->pivot == RQRCP_PIVOT_ORTHO;
   P.fixed = o->fixed_pivots != 0;
+  P.power = P.fixed ? 0 : o->power;
   P.classical_tail = !P.ortho && !P.fixed && o->tail == RQRCP_TAIL_CLASSICAL && P.k == n;
   if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
   if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
@@ -164,6 +170,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
         Yd = std::max(Yd, (size_t)(P.ks * ni));
         const int64_t yrows = P.ortho ? bi : P.ks;
         gpart = std::max(gpart, gemm_part_doubles(yrows, ni, mi));
+        if (P.power > 0) gpart = std::max(gpart, gemm_part_doubles(yrows, mi, ni));
         if (P.f32 && P.mixed) spart = std::max(spart, sample_bf16_part_floats(yrows, ni, mi));
         if (P.f32 && !P.mixed) gpart32 = std::max(gpart32, gemm_part_doubles(yrows, ni, mi));
         if (P.ortho) {
@@ -197,7 +204,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (!P.f32) gpart32 = 0;
   // the next block's sketch product and this block's trailing update may run
   // on the auxiliary stream (own split-K room), the correction G V on the main
-  P.pipe = !P.f32 && !P.ortho && !P.fixed;
+  P.pipe = !P.f32 && !P.ortho && !P.fixed && P.power == 0;
   size_t gpaux = 0;
   if (P.pipe)
     for (int64_t i = 0; i + 1 < P.nblocks; ++i) {
@@ -240,6 +247,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.gpart_aux = w.take(gpaux * d);
   P.vtpart = w.take(vtp * d);
   P.W2 = w.take(P.f32 ? 0 : (size_t)P.b * n * d);
+  P.Z = w.take(P.power > 0 ? (size_t)P.ks * m * d : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -505,6 +513,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   double *GVb = at<double>(work, P.GVb), *gpart_aux = at<double>(work, P.gpart_aux);
   double *vtpart = at<double>(work, P.vtpart);
   double *W2 = at<double>(work, P.W2);
+  double *Z = at<double>(work, P.Z);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -612,6 +621,18 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
               GemmF32 gy{false, false, yrows, ni, mi, G32, ks, X, lda, Y32, ks, 1.f, 0.f};
               CHK(launch_gemm<float>(s, gy, gpart32), "FP32 sketch product");
               CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
+            }
+          }
+          // Section 6.3: q steps of the power iteration in the row form of the
+          // sample, Y_i := (Y_i X_i^T) X_i, so that Y_i = G_i X_i (X_i^T X_i)^q
+          if constexpr (!F32) {
+            for (int q = 0; q < P.power; ++q) {
+              ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
+                             16.0 * mi * ni + 16.0 * yrows * (mi + ni));
+              GemmF64 gz{false, true, yrows, mi, ni, Y, ks, X, lda, Z, ks, 1.0, 0.0};
+              CHK(launch_gemm_f64(s, gz, gpart), "power iteration Y X^T");
+              GemmF64 gy{false, false, yrows, ni, mi, Z, ks, X, lda, Y, ks, 1.0, 0.0};
+              CHK(launch_gemm_f64(s, gy, gpart), "power iteration (Y X^T) X");
             }
           }
         }
