@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true", help="skip the bwd/fwd ratio measurement (C5)")
     ap.add_argument("--power", type=int, default=1,
                     help="also time the workload with this many power-iteration steps (Section 6.3); 0 skips")
+    ap.add_argument("--no-panel-pivot", action="store_true",
+                    help="skip timing the workload with Fig. 3's in-block pivot P-hat")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain copy-like kernel (torch.neg) over 2^26 doubles, to scale HBM counters")
     return ap.parse_args()
@@ -172,7 +174,7 @@ def main():
     A = W.workload_matrix(w, device=dev)
     m, n = A.shape
 
-    def run(wl, Ain, steps, warmup, profile, check=True, power=0):
+    def run(wl, Ain, steps, warmup, profile, check=True, power=0, panel_pivot=False):
         """Time `steps` factorizations of Ain (already resident) with HIP events.
 
         Inside the timed steps only the W = V^T C and trailing-update launches
@@ -184,7 +186,8 @@ def main():
         A0 = R.colmajor(Ain.to(dtype))
         F = torch.empty_like(A0)
         sizes = R.factor_sizes(m, n, dtype, block=wl.b, oversample=wl.p, pivot=wl.pivot, rank=wl.rank,
-                               precision="mixed" if wl.precision == "mixed" else "plain", power=power)
+                               precision="mixed" if wl.precision == "mixed" else "plain", power=power,
+                               panel_pivot=panel_pivot)
         jp = torch.empty(n, dtype=torch.int32, device=dev)
         tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
         T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
@@ -192,7 +195,7 @@ def main():
         work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
         info = torch.zeros(4, dtype=torch.int32, device=dev)
         kw = dict(block=wl.b, oversample=wl.p, seed=wl.seed, pivot=wl.pivot, rank=wl.rank, info=info,
-                  precision="mixed" if wl.precision == "mixed" else "plain", power=power)
+                  precision="mixed" if wl.precision == "mixed" else "plain", power=power, panel_pivot=panel_pivot)
         for _ in range(warmup):
             F.copy_(A0)
             R.factor_into(F, jp, tau, T, S, work, **kw)
@@ -264,6 +267,17 @@ def main():
                  "residual": pres, "info": pinfo,
                  "breakdown": {k: v[1] / args.steps for k, v in pprof.items()}}
 
+    # the same factorization with Fig. 3's in-block pivot P-hat (a QRCP of
+    # every panel's R', the panel restored, permuted and factored again)
+    phat = None
+    if not args.no_panel_pivot and w.precision != "mixed" and w.pivot == "perm":
+        ht, (_, hprof), hres, hinfo = run(w, A, args.steps, args.warmup, True, check=not args.no_residual,
+                                          panel_pivot=True)
+        hms = float(np.mean(ht))
+        phat = {"workload": f"{w.name} with the in-block pivot P-hat", "ms_per_step": hms,
+                "value": flops / (hms * 1e-3) / 1e9, "slowdown_vs_identity": hms / ms, "residual": hres,
+                "info": hinfo, "breakdown": {k: v[1] / args.steps for k, v in hprof.items()}}
+
     # roofline of the dominant matrix-core kernel on the critical path: W = V^T C
     # (the sketch product and the trailing update run on the capped auxiliary
     # stream, overlapped with the panel and the pivoted QR; reported below)
@@ -300,7 +314,7 @@ def main():
         "roofline": roof,
         "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "latency": latency,
                   "update_overlapped": update_overlapped,
-                  "mixed": mixed, "power_iteration": power},
+                  "mixed": mixed, "power_iteration": power, "panel_pivot": phat},
     }
     if not args.no_bwd:
         out["extra"]["bwd_fwd"] = bwd_fwd_ratio()

@@ -98,6 +98,12 @@ typedef struct {
                         /* needs FP64 storage (else RQRCP_ERR_UNSUPPORTED), turns the  */
                         /* overlapped schedule off and takes (b+p) m more doubles of   */
                         /* workspace; ignored with fixed_pivots                        */
+  int32_t panel_pivot;  /* 1: Fig. 3's in-block pivot P-hat, a QR with column pivoting */
+                        /* of every sketched panel (its order read off a QRCP of the   */
+                        /* panel's R', the Remark of Section 2); the columns above the */
+                        /* panel and jpvt follow.  FP64 storage and the permutation    */
+                        /* form only (else RQRCP_ERR_UNSUPPORTED); ignored with        */
+                        /* fixed_pivots.  0 (default): P-hat = I                       */
 } rqrcp_opts_t;
 
 /* Default options: b = 128, p = 10, full rank, permutation, plain, classical

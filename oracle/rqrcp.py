@@ -28,7 +28,8 @@ Conventions (the readings of the paper this oracle takes):
   first b_i = min(b, columns left) steps of the QR process on Y_i run.  The
   pivot matrix is applied to columns r0:n of all m rows.  The panel
   A(r0:m, r0:r0+b_i) is factored by unpivoted Householder QR (the in-block
-  pivot P-hat of Fig. 3 is the identity), and the trailing matrix is updated
+  pivot P-hat of Fig. 3 is the identity; with panel_pivot it is the pivot
+  of a classical QRCP of the panel), and the trailing matrix is updated
   with the compact WY form of the panel's reflectors (Section 5.1).
 * n need not be a multiple of b: the last block takes what is left.  With a
   full factorization the last block is the "tail" of Fig. 3 and gets a
@@ -190,7 +191,7 @@ def sketch(seed, block, nsample, row0, nrows):
 
 
 def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
-          sampler="gaussian", trace=False, power=0):
+          sampler="gaussian", trace=False, power=0, panel_pivot=False):
     """Blocked randomized QR (Fig. 3) of a copy of A; returns a dict.
 
     pivot   : "perm" (Section 4.1) or "ortho" (Section 4.2)
@@ -201,6 +202,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
     sampler : "gaussian", or "identity" (Y_i := X_i; test reduction only)
     power   : q >= 0 steps of the power iteration of Section 6.3 on each
               sketched block: Y_i := G_i X_i (X_i^T X_i)^q
+    panel_pivot : Fig. 3's in-block pivot P-hat (permutation form): the
+              panel of every sketched block is factored by classical QRCP
+              (Fig. 2) instead of unpivoted Householder QR, and its swaps
+              reorder the columns above the panel and jpvt as well
 
     Output keys: F (R on and above the diagonal, Householder vectors below),
     tau, T (list of per-block T), jpvt, S (list of (V_S, tau_S, T_S) per block
@@ -220,7 +225,7 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
     jpvt = np.arange(n)
     tau = np.zeros(k)
     out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": [], "xnorm": [], "ynorm": [],
-           "tops": []}
+           "tops": [], "pmargins": [], "ptops": [], "pnorm": []}
     nblocks = -(-k // b)
     for i in range(nblocks):
         r0 = i * b
@@ -280,9 +285,23 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
             C = A[:, r0:]
             C -= ((C @ VS) @ TS) @ VS.T
             out["S"].append((VS, ts, TS))
-        # unpivoted Householder QR of the panel (P-hat = I)
         panel = A[r0:, r0:r0 + bi]
-        t = householder_qr(panel, steps=bi)
+        if panel_pivot and pivot == "perm":
+            # Fig. 3 with P-hat: QR with column pivoting of the panel; qrcp
+            # swaps the panel's own rows in place, the rows above follow
+            out["pnorm"].append(float(np.linalg.norm(panel)))
+            tp = []
+            ppiv, _, t, pmg = qrcp(panel, steps=bi, record_margins=True, tops=tp)
+            for j in range(bi):
+                jj = int(ppiv[j])
+                if jj != j:
+                    A[:r0, [r0 + j, r0 + jj]] = A[:r0, [r0 + jj, r0 + j]]
+                    jpvt[[r0 + j, r0 + jj]] = jpvt[[r0 + jj, r0 + j]]
+            out["pmargins"].append(pmg)
+            out["ptops"].append(np.array(tp))
+        else:
+            # unpivoted Householder QR of the panel (P-hat = I)
+            t = householder_qr(panel, steps=bi)
         tau[r0:r0 + bi] = t
         V = unit_lower(A[r0:, r0:r0 + bi], mi, bi)
         T = wy_T(V, t)

@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
         ("block", ctypes.c_int64), ("oversample", ctypes.c_int64), ("rank", ctypes.c_int64),
         ("pivot", ctypes.c_int32), ("precision", ctypes.c_int32), ("tail", ctypes.c_int32),
         ("fixed_pivots", ctypes.c_int32), ("seed", ctypes.c_uint64), ("G", ctypes.c_void_p),
-        ("info", ctypes.c_void_p), ("power", ctypes.c_int32),
+        ("info", ctypes.c_void_p), ("power", ctypes.c_int32), ("panel_pivot", ctypes.c_int32),
     ]
 
 
@@ -150,7 +150,7 @@ def _dt(t):
 
 
 def make_opts(block=128, oversample=10, rank=0, pivot="perm", precision="plain", tail="classical",
-              fixed_pivots=False, seed=0, G=None, info=None, power=0):
+              fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False):
     o = Opts()
     o.block, o.oversample, o.rank = int(block), int(oversample), int(rank)
     o.pivot, o.precision, o.tail = PIVOT[pivot], PRECISION[precision], TAIL[tail]
@@ -159,6 +159,7 @@ def make_opts(block=128, oversample=10, rank=0, pivot="perm", precision="plain",
     o.G = G.data_ptr() if G is not None else None
     o.info = info.data_ptr() if info is not None else None
     o.power = int(power)
+    o.panel_pivot = 1 if panel_pivot else 0
     return o
 
 
@@ -198,28 +199,30 @@ class Workspace:
 
 
 def factor_into(F, jpvt, tau, T, S, work, *, block=128, oversample=10, rank=0, pivot="perm", precision="plain",
-                tail="classical", fixed_pivots=False, seed=0, G=None, info=None, power=0):
+                tail="classical", fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False):
     """rqrcp_factor on caller-owned buffers (F is factored in place)."""
     L = load_library()
     m, n = F.shape
-    o = make_opts(block, oversample, rank, pivot, precision, tail, fixed_pivots, seed, G, info, power)
+    o = make_opts(block, oversample, rank, pivot, precision, tail, fixed_pivots, seed, G, info, power, panel_pivot)
     h = handle(F.device)
     _check(L.rqrcp_factor(h, _dt(F), m, n, _ptr(F), _ld(F), _ptr(jpvt), _ptr(tau), _ptr(T), _ptr(S),
                           ctypes.byref(o), _ptr(work), work.numel()), h)
 
 
 def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain", rank=0, tail="classical",
-           G=None, jpvt=None, info=None, workspace=None, power=0) -> Factorization:
+           G=None, jpvt=None, info=None, workspace=None, power=0, panel_pivot=False) -> Factorization:
     """A P = Q R by blocked randomized QRCP.  A is not modified.
 
     jpvt: optional int32[n] of fixed pivots (factor A(:, jpvt) without any
     sketch; permutation form only).  power: q steps of the power iteration
-    of Section 6.3 on every sketch (FP64 storage)."""
+    of Section 6.3 on every sketch (FP64 storage).  panel_pivot: Fig. 3's
+    in-block pivot P-hat (FP64 storage, permutation form)."""
     m, n = A.shape
     F = colmajor(A)
     kk = n if rank in (0, None) else int(rank)
     sizes = factor_sizes(m, n, A.dtype, block=block, oversample=oversample, rank=kk, pivot=pivot,
-                         precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, power=power)
+                         precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, power=power,
+                         panel_pivot=panel_pivot)
     dev = A.device
     tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
     T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
@@ -229,7 +232,7 @@ def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain",
     work = ws.get(sizes[3], dev)
     factor_into(F, jp, tau, T, S, work, block=block, oversample=oversample, rank=kk, pivot=pivot,
                 precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, G=G, info=info,
-                power=power)
+                power=power, panel_pivot=panel_pivot)
     return Factorization(F, jp, tau, T, S, int(block), kk, pivot)
 
 

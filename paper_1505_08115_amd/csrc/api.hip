@@ -92,6 +92,7 @@ struct FactorPlan {
   int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
   bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
   int power = 0;   // steps of the power iteration on every sketched block
+  bool panel_pivot = false;   // in-block pivot P-hat by QRCP of the panel's R'
   // FP32-storage buffers
   size_t Pw = 0, V32 = 0, VT32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
   int nslots = 0;
@@ -105,6 +106,7 @@ struct FactorPlan {
   size_t vtpart = 0;   // split-K buffer of V T^T (on the side stream, beside W)
   size_t W2 = 0;       // T^T W (overlapped schedule)
   size_t Z = 0;        // Y X^T of the power iteration
+  size_t Pc = 0, Rp = 0;   // saved panel and its R' (in-block pivoting)
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -134,6 +136,9 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->power < 0 || o->power > 8) return fail(h, RQRCP_ERR_ARG, "opts.power must be in [0, 8]");
   if (o->power > 0 && dt != RQRCP_F64 && !o->fixed_pivots)
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only in this build");
+  if (o->panel_pivot != 0 && o->panel_pivot != 1) return fail(h, RQRCP_ERR_ARG, "opts.panel_pivot must be 0 or 1");
+  if (o->panel_pivot && !o->fixed_pivots && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_PERM))
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: FP64 storage and the permutation form only");
   FactorPlan P;
   P.f32 = dt == RQRCP_F32;
   P.mixed = o->precision == RQRCP_PREC_MIXED;
@@ -144,6 +149,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.ortho = o->pivot == RQRCP_PIVOT_ORTHO;
   P.fixed = o->fixed_pivots != 0;
   P.power = P.fixed ? 0 : o->power;
+  P.panel_pivot = !P.fixed && o->panel_pivot != 0;
   P.classical_tail = !P.ortho && !P.fixed && o->tail == RQRCP_TAIL_CLASSICAL && P.k == n;
   if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
   if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
@@ -189,6 +195,12 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
           if (qn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "sketch too large for the pivoted-QR kernel");
           qnwg = std::max(qnwg, qn);
           qk = std::max(qk, P.ks);
+          if (P.panel_pivot) {
+            const int qp = qrcp_small_config((int)bi, (int)bi, &cpw);
+            if (qp == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "block too large for the pivoted QR of the panel's R'");
+            qnwg = std::max(qnwg, qp);
+            qk = std::max(qk, bi);
+          }
         }
       }
     }
@@ -218,7 +230,9 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));     // T^T W
     }
   P.Y_doubles = Yd;
-  P.nslots = (int)(3 * P.nblocks + 4);
+  // cooperative launches per block: pivoted QR of the sketch (or the
+  // orthonormal form's panel), the panel, and with P-hat one more of each
+  P.nslots = (int)((P.panel_pivot ? 5 : 3) * P.nblocks + 4);
   Bump w;
   const size_t d = sizeof(double);
   P.G = w.take((o->G || P.fixed) ? 0 : (size_t)P.ks * m * d);
@@ -248,6 +262,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.vtpart = w.take(vtp * d);
   P.W2 = w.take(P.f32 ? 0 : (size_t)P.b * n * d);
   P.Z = w.take(P.power > 0 ? (size_t)P.ks * m * d : 0);
+  P.Pc = w.take(P.panel_pivot ? (size_t)m * P.b * d : 0);
+  P.Rp = w.take(P.panel_pivot ? (size_t)P.b * P.b * d : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -514,6 +530,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   double *vtpart = at<double>(work, P.vtpart);
   double *W2 = at<double>(work, P.W2);
   double *Z = at<double>(work, P.Z);
+  double *Pc = at<double>(work, P.Pc), *Rp = at<double>(work, P.Rp);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -708,6 +725,35 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         gy.max_wg = beside_panel;
         CHK(launch_gemm_f64(aux, gy, gpart_aux), "sketch product of the next block");
       }
+    }
+    // Fig. 3's in-block pivot P-hat (FP64 permutation form): a QR with column
+    // pivoting of the panel.  Its pivot order depends on the columns only
+    // through their Gram matrix, which the triangular factor R' of an
+    // unpivoted QR of the panel shares (the Remark of Section 2), so the
+    // order is read off a QRCP of the b_i x b_i R'; the saved panel is then
+    // restored, its columns (all m rows) and jpvt permuted, and the pivoted
+    // panel factored below like any other.
+    if constexpr (!F32) if (P.panel_pivot && !block_is_classical_tail(P, i)) {
+      {
+        ScopedTimer tp(h, RQRCP_K_PANEL, 2.0 * mi * bi * bi - 2.0 * bi * bi * bi / 3.0, 40.0 * mi * bi);
+        CHK(launch_copy2d(s, X, lda, Pc, mi, mi, bi), "save the panel");
+        PanelQR pq{};
+        pq.P = X; pq.ldp = lda; pq.mi = mi; pq.nb = (int)bi;
+        pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+        pq.VT = nullptr; pq.ldvt = b;
+        pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
+        next_slot(&pq.bar, &pq.abort_flag);
+        CHK(launch_panel_qr(s, pq), "unpivoted QR of the panel");
+        CHK(launch_extract_r(s, X, lda, bi, bi, Rp, bi), "R' of the panel");
+      }
+      {
+        ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)bi, (double)bi, (double)bi), 8.0 * bi * bi);
+        CHK(run_qrcp(Rp, bi, bi, bi, bi, i), "pivoted QR of R'");
+      }
+      ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 16.0 * mi * bi + 32.0 * bi * m);
+      CHK(launch_copy2d(s, Pc, mi, X, lda, mi, bi), "restore the panel");
+      CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
+          "move the panel's columns");
     }
     // panel: unpivoted Householder QR of A(r0:m, r0:r0+bi) in FP64
     {

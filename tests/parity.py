@@ -24,12 +24,21 @@ def separated_prefix(res, noise=NOISE):
     if not res["margins"]:
         return 0
     nA = res["xnorm"][0]
-    for (r0, bi), mg, xn, yn, tops in zip(res["blocks"], res["margins"], res["xnorm"], res["ynorm"],
-                                           res["tops"]):
+    pm, pt = res.get("pmargins", []), res.get("ptops", [])
+    for i, ((r0, bi), mg, xn, yn, tops) in enumerate(zip(res["blocks"], res["margins"], res["xnorm"], res["ynorm"],
+                                                          res["tops"])):
         for j in range(bi):
             delta = noise * U * (nA / max(xn, 1e-300)) * (yn / max(tops[j], 1e-300))
             if not (mg[j] > delta):
-                return r0 + j
+                # with the in-block pivot P-hat a column chosen differently
+                # may land anywhere in the block
+                return r0 + j if i >= len(pm) else r0
+        if i < len(pm):
+            # P-hat: QRCP of the panel, whose residual norms carry absolute
+            # differences of a few u |A|
+            for j in range(bi):
+                if not (pm[i][j] > noise * U * nA / max(pt[i][j], 1e-300)):
+                    return r0 + j
     return res["rank"]
 
 

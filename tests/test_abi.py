@@ -52,7 +52,7 @@ def test_default_options_and_status_strings(lib):
     o = R.Opts()
     lib.rqrcp_default_opts(ctypes.byref(o))
     assert (o.block, o.oversample, o.rank, o.pivot, o.precision, o.tail, o.fixed_pivots) == (128, 10, 0, 0, 0, 0, 0)
-    assert o.seed == 0 and not o.G and not o.info and o.power == 0
+    assert o.seed == 0 and not o.G and not o.info and o.power == 0 and o.panel_pivot == 0
     for st in range(6):
         assert lib.rqrcp_status_string(st)
 
@@ -79,6 +79,7 @@ def test_factor_sizes_follow_the_block_structure(lib):
     (2000, 2000, {"block": 400, "oversample": 200}, ERR_UNSUPPORTED),   # b + p > 512
     (100, 100, {"power": -1}, ERR_ARG),                     # q < 0
     (100, 100, {"power": 9}, ERR_ARG),                      # q > 8
+    (100, 100, {"pivot": "ortho", "panel_pivot": True}, ERR_UNSUPPORTED),  # P-hat: permutation form only
 ])
 def test_factor_sizes_rejects_invalid_arguments(lib, m, n, kw, status):
     o = R.make_opts(**kw)
@@ -89,11 +90,14 @@ def test_factor_sizes_rejects_invalid_arguments(lib, m, n, kw, status):
     assert lib.rqrcp_last_error(None)
 
 
-def test_power_iteration_needs_fp64_storage(lib):
+def test_power_iteration_and_panel_pivoting_need_fp64_storage(lib):
     a, b, c, d = (ctypes.c_size_t() for _ in range(4))
     args = (ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d))
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1)), *args) == ERR_UNSUPPORTED
     assert lib.rqrcp_factor_sizes(0, 500, 400, ctypes.byref(R.make_opts(power=2)), *args) == 0
+    # P-hat needs FP64 storage as well
+    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == ERR_UNSUPPORTED
+    assert lib.rqrcp_factor_sizes(0, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == 0
     # fixed pivots draw no sketch: the power setting is ignored
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1, fixed_pivots=True)), *args) == 0
 

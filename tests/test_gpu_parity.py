@@ -555,3 +555,37 @@ def test_power_iteration_matches_oracle(m, n, b, p, pivot, rank, tail, q, shared
         assert pre >= min(b, k), f"only {pre} separated decisions"
     _invariants(A, Fz)
     np.testing.assert_allclose(np.abs(Fz.tau.cpu().numpy()[:k]), np.abs(ref["tau"][:k]), atol=1e-8)
+
+
+PHAT = [
+    # m, n, b, p, rank, tail, q, shared sketch
+    (64, 64, 8, 4, 0, "classical", 0, True),
+    (300, 250, 32, 5, 0, "classical", 0, True),      # ragged last block, m > n
+    (257, 257, 16, 8, 0, "sampled", 0, True),        # the sampled tail gets P-hat too
+    (400, 300, 64, 10, 100, "classical", 1, True),   # truncated rank, with the power iteration
+    (1200, 1000, 128, 16, 0, "classical", 0, False),
+    (1500, 1100, 256, 10, 0, "classical", 0, False),  # 256 x 256 R'
+]
+
+
+@pytest.mark.parametrize("m,n,b,p,rank,tail,q,shared", PHAT)
+def test_panel_pivoting_matches_oracle(m, n, b, p, rank, tail, q, shared):
+    """Fig. 3's in-block pivot P-hat: every sketched panel by QR with column
+    pivoting (the order read off a QRCP of the panel's R')."""
+    progress(f"panel pivoting m={m} n={n} b={b} p={p} rank={rank} {tail} q={q}")
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 6.0), seed=m + n + 5).numpy()
+    k = n if rank == 0 else rank
+    blocks = _oracle_G(13, m, n, b, p, k, tail == "classical") if shared else None
+    ref = O.rqrcp(A, b, p, seed=13, rank=rank, tail=tail, G=blocks or None, power=q, panel_pivot=True)
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=p, seed=13, rank=rank, tail=tail,
+                  G=_g_hook(blocks) if shared else None, power=q, panel_pivot=True)
+    torch.cuda.synchronize()
+    pre = _compare(A, Fz, ref)
+    assert pre >= min(b, k), f"only {pre} separated decisions"
+    _invariants(A, Fz)
+    np.testing.assert_allclose(np.abs(Fz.tau.cpu().numpy()[:k]), np.abs(ref["tau"][:k]), atol=1e-8)
+    # QRCP orders every block by decreasing |R_jj|
+    d = np.abs(np.diag(Fz.F.cpu().numpy()))[:k]
+    for r0 in range(0, k, b):
+        blk = d[r0:min(k, r0 + b)]
+        assert np.all(blk[:-1] >= blk[1:] * (1 - 1e-12)), f"block at {r0}"
