@@ -191,7 +191,7 @@ def sketch(seed, block, nsample, row0, nrows):
 
 
 def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
-          sampler="gaussian", trace=False, power=0, panel_pivot=False):
+          sampler="gaussian", trace=False, power=0, panel_pivot=False, diagonalize=False):
     """Blocked randomized QR (Fig. 3) of a copy of A; returns a dict.
 
     pivot   : "perm" (Section 4.1) or "ortho" (Section 4.2)
@@ -206,6 +206,10 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
               panel of every sketched block is factored by classical QRCP
               (Fig. 2) instead of unpivoted Householder QR, and its swaps
               reorder the columns above the panel and jpvt as well
+    diagonalize : Section 6.2 (with pivot="ortho": blockRRQR, Fig. 5): the
+              b_i x b_i triangle R22 of every panel is replaced by its
+              singular values, R22 = U' D V'^T; U'^T rotates the block's
+              rows to the right of it, V' its columns above it and P
 
     Output keys: F (R on and above the diagonal, Householder vectors below),
     tau, T (list of per-block T), jpvt, S (list of (V_S, tau_S, T_S) per block
@@ -219,13 +223,15 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
     m, n = A.shape
     if m < n:
         raise ValueError("the method assumes m >= n")
+    if diagonalize and pivot != "ortho":
+        raise ValueError("the diagonalised blocks (Section 6.2) go with orthonormal pivoting")
     k = n if rank in (0, None) else int(rank)
     if not 1 <= k <= n:
         raise ValueError("rank out of range")
     jpvt = np.arange(n)
     tau = np.zeros(k)
     out = {"T": [], "S": [], "piv": [], "margins": [], "Y": [], "blocks": [], "xnorm": [], "ynorm": [],
-           "tops": [], "pmargins": [], "ptops": [], "pnorm": []}
+           "tops": [], "pmargins": [], "ptops": [], "pnorm": [], "D": []}
     nblocks = -(-k // b)
     for i in range(nblocks):
         r0 = i * b
@@ -310,6 +316,20 @@ def rqrcp(A, b, p, seed, pivot="perm", rank=0, tail="classical", G=None,
         C = A[r0:, r0 + bi:]
         if C.shape[1]:
             C -= V @ (T.T @ (V.T @ C))
+        if diagonalize:
+            # Section 6.2: R22 = U' D V'^T (full SVD of the b_i x b_i triangle);
+            # U-tilde = Q-tilde diag(U', I) puts U'^T on the block's rows right
+            # of it, V-tilde = V' multiplies the block's columns above it (and
+            # P); the triangle becomes D, the reflectors below it stay
+            R22 = np.triu(A[r0:r0 + bi, r0:r0 + bi])
+            U1, d, V1t = np.linalg.svd(R22)
+            V1 = V1t.T
+            A[r0:r0 + bi, r0 + bi:] = U1.T @ A[r0:r0 + bi, r0 + bi:]
+            A[:r0, r0:r0 + bi] = A[:r0, r0:r0 + bi] @ V1
+            blk = A[r0:r0 + bi, r0:r0 + bi]
+            blk[np.triu_indices(bi)] = 0.0
+            blk[np.arange(bi), np.arange(bi)] = d
+            out["D"].append((U1, V1))
     out.update(F=A, tau=tau, jpvt=jpvt, rank=k, b=b, p=p, pivot=pivot)
     return out
 
@@ -329,14 +349,21 @@ def block_reflectors(res):
 
 
 def apply_q(res, C, trans):
-    """Q C (trans=False) or Q^T C (trans=True), Q = prod_i diag(I, I - V_i T_i V_i^T)."""
+    """Q C (trans=False) or Q^T C (trans=True), Q = prod_i diag(I, Q_i) with
+    Q_i = I - V_i T_i V_i^T, times diag(U'_i, I) for diagonalised blocks."""
     C = np.array(C, dtype=np.float64, copy=True)
     blocks = block_reflectors(res)
-    seq = blocks if trans else blocks[::-1]
-    for r0, V, T in seq:
+    Us = [u for u, _ in res.get("D", [])] or [None] * len(blocks)
+    seq = list(zip(blocks, Us))
+    for (r0, V, T), U1 in (seq if trans else seq[::-1]):
+        bi = V.shape[1]
+        if U1 is not None and not trans:
+            C[r0:r0 + bi] = U1 @ C[r0:r0 + bi]
         Tt = T.T if trans else T
         Cs = C[r0:]
         Cs -= V @ (Tt @ (V.T @ Cs))
+        if U1 is not None and trans:
+            C[r0:r0 + bi] = U1.T @ C[r0:r0 + bi]
     return C
 
 
@@ -355,9 +382,12 @@ def form_p(res):
         P[res["jpvt"], np.arange(n)] = 1.0
         return P
     P = np.eye(n)
-    for (r0, _), (VS, _, TS) in zip(res["blocks"], res["S"]):
+    Vs = [v for _, v in res.get("D", [])] or [None] * len(res["S"])
+    for (r0, bi), (VS, _, TS), V1 in zip(res["blocks"], res["S"], Vs):
         Pc = P[:, r0:]
         Pc -= ((Pc @ VS) @ TS) @ VS.T
+        if V1 is not None:
+            P[:, r0:r0 + bi] = P[:, r0:r0 + bi] @ V1
     return P
 
 
