@@ -156,6 +156,41 @@ def bwd_fwd_ratio(reps=5, dtype=None):
             "recompute_vs_kept_rel_diff": agree, "dtype": "f64" if dtype == torch.float64 else "f32"}
 
 
+def methods_123(reps=3):
+    """Section 7's three methods on the 1024^2 matrix with a spectral gap
+    (C3's subcase): Method 1 (permutation, p = 10), Method 2 (orthonormal
+    pivoting, p = b/2) and blockRRQR (Method 3: orthonormal pivoting, q = 2
+    power steps, diagonalised blocks, p = b/2), b = 64.  Median HIP-event
+    times and how closely |R_kk| follows sigma_k (median |log|)."""
+    import numpy as np
+    import torch
+
+    import paper_1505_08115_amd as R
+    import workloads as W
+    w = W.WORKLOADS["C3s"]
+    dev = torch.device("cuda:0")
+    A = R.colmajor(W.workload_matrix(w, device=dev))
+    s = np.asarray(w.sigma(), dtype=np.float64)
+    b = 64
+    out = {"workload": f"C3s: {w.m}x{w.n} FP64, sigma with a 1e-6 gap after 256, b={b}"}
+    for name, kw in (("method1", dict(pivot="perm", oversample=10)),
+                     ("method2", dict(pivot="ortho", oversample=b // 2)),
+                     ("method3", dict(pivot="ortho", oversample=b // 2, power=2, diagonalize=True))):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            Fz = R.factor(A, block=b, seed=w.seed, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        d = np.abs(np.diag(Fz.F.cpu().numpy()))
+        out[name] = {"ms": float(np.median(ts[1:])),
+                     "median_abs_log_rkk_over_sigma": float(np.median(np.abs(np.log(d / s))))}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -317,6 +352,7 @@ def main():
                   "mixed": mixed, "power_iteration": power, "panel_pivot": phat},
     }
     if not args.no_bwd:
+        out["extra"]["methods_123"] = methods_123()
         out["extra"]["bwd_fwd"] = bwd_fwd_ratio()
         out["extra"]["bwd_fwd_fp32"] = bwd_fwd_ratio(dtype=torch.float32)
     if args.calibrate:

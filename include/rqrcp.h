@@ -104,6 +104,16 @@ typedef struct {
                         /* panel and jpvt follow.  FP64 storage and the permutation    */
                         /* form only (else RQRCP_ERR_UNSUPPORTED); ignored with        */
                         /* fixed_pivots.  0 (default): P-hat = I                       */
+  int32_t diagonalize;  /* 1: diagonalised blocks of Section 6.2 (with ORTHO pivoting   */
+                        /* and power: blockRRQR, Fig. 5): each block's b_i x b_i       */
+                        /* triangle R22 = U' D V'^T becomes D (decreasing, >= 0), its  */
+                        /* rows right of it get U'^T and its columns above it V'.      */
+                        /* Q = prod_i diag(I, (I - V_i T_i V_i^T) diag(U'_i, I)) and   */
+                        /* P = prod_i diag(I, S_i) diag(I, V'_i, I); U'_i, V'_i (b x b, */
+                        /* ld b) follow the T_S blocks in S (see rqrcp_factor).  FP64, */
+                        /* ORTHO and b <= 64 only (else RQRCP_ERR_UNSUPPORTED).        */
+                        /* rqrcp_apply_q/_apply_p/_lowrank/_lowrank_backward do not    */
+                        /* read U' or V': they cover factorizations without it         */
 } rqrcp_opts_t;
 
 /* Default options: b = 128, p = 10, full rank, permutation, plain, classical
@@ -136,7 +146,11 @@ rqrcp_status_t rqrcp_factor_sizes(rqrcp_dtype_t dt, int64_t m, int64_t n, const 
  *        columns k:n hold the updated trailing matrix R_22 of Section 6.1.
  *   jpvt (out, or in with fixed_pivots) int32[n].
  *   tau  (out) double[k];  T (out) double[ceil(k/b) * b * b].
- *   S    (out) ORTHO only, double[S_elems]; must be NULL for PERM.
+ *   S    (out) ORTHO only, double[S_elems]; must be NULL for PERM.  Layout:
+ *        the reflectors V_S of every block ((n - i b) x b, ld n - i b, one
+ *        block after the other), then tau_S (nblocks x b), then T_S
+ *        (nblocks blocks of b x b, ld b), then with diagonalize U'_i and
+ *        V'_i for every block (b x b each, ld b, U'_0 V'_0 U'_1 V'_1 ...).
  *   work, work_bytes: device workspace of at least rqrcp_factor_sizes bytes,
  *        256-byte aligned; its contents on entry do not matter.
  * Precision: dt = F64 computes in FP64 throughout.  dt = F32 stores A in

@@ -52,6 +52,7 @@ class Opts(ctypes.Structure):
         ("pivot", ctypes.c_int32), ("precision", ctypes.c_int32), ("tail", ctypes.c_int32),
         ("fixed_pivots", ctypes.c_int32), ("seed", ctypes.c_uint64), ("G", ctypes.c_void_p),
         ("info", ctypes.c_void_p), ("power", ctypes.c_int32), ("panel_pivot", ctypes.c_int32),
+        ("diagonalize", ctypes.c_int32),
     ]
 
 
@@ -150,7 +151,7 @@ def _dt(t):
 
 
 def make_opts(block=128, oversample=10, rank=0, pivot="perm", precision="plain", tail="classical",
-              fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False):
+              fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False, diagonalize=False):
     o = Opts()
     o.block, o.oversample, o.rank = int(block), int(oversample), int(rank)
     o.pivot, o.precision, o.tail = PIVOT[pivot], PRECISION[precision], TAIL[tail]
@@ -160,6 +161,7 @@ def make_opts(block=128, oversample=10, rank=0, pivot="perm", precision="plain",
     o.info = info.data_ptr() if info is not None else None
     o.power = int(power)
     o.panel_pivot = 1 if panel_pivot else 0
+    o.diagonalize = 1 if diagonalize else 0
     return o
 
 
@@ -184,6 +186,7 @@ class Factorization:
     block: int
     rank: int
     pivot: str
+    diagonalized: bool = False    # Section 6.2: U'_i, V'_i stored in S after the T_S blocks
 
 
 class Workspace:
@@ -199,30 +202,34 @@ class Workspace:
 
 
 def factor_into(F, jpvt, tau, T, S, work, *, block=128, oversample=10, rank=0, pivot="perm", precision="plain",
-                tail="classical", fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False):
+                tail="classical", fixed_pivots=False, seed=0, G=None, info=None, power=0, panel_pivot=False,
+                diagonalize=False):
     """rqrcp_factor on caller-owned buffers (F is factored in place)."""
     L = load_library()
     m, n = F.shape
-    o = make_opts(block, oversample, rank, pivot, precision, tail, fixed_pivots, seed, G, info, power, panel_pivot)
+    o = make_opts(block, oversample, rank, pivot, precision, tail, fixed_pivots, seed, G, info, power, panel_pivot,
+                  diagonalize)
     h = handle(F.device)
     _check(L.rqrcp_factor(h, _dt(F), m, n, _ptr(F), _ld(F), _ptr(jpvt), _ptr(tau), _ptr(T), _ptr(S),
                           ctypes.byref(o), _ptr(work), work.numel()), h)
 
 
 def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain", rank=0, tail="classical",
-           G=None, jpvt=None, info=None, workspace=None, power=0, panel_pivot=False) -> Factorization:
+           G=None, jpvt=None, info=None, workspace=None, power=0, panel_pivot=False,
+           diagonalize=False) -> Factorization:
     """A P = Q R by blocked randomized QRCP.  A is not modified.
 
     jpvt: optional int32[n] of fixed pivots (factor A(:, jpvt) without any
     sketch; permutation form only).  power: q steps of the power iteration
     of Section 6.3 on every sketch (FP64 storage).  panel_pivot: Fig. 3's
-    in-block pivot P-hat (FP64 storage, permutation form)."""
+    in-block pivot P-hat (FP64 storage, permutation form).  diagonalize:
+    Section 6.2's diagonal blocks (with pivot="ortho": blockRRQR)."""
     m, n = A.shape
     F = colmajor(A)
     kk = n if rank in (0, None) else int(rank)
     sizes = factor_sizes(m, n, A.dtype, block=block, oversample=oversample, rank=kk, pivot=pivot,
                          precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, power=power,
-                         panel_pivot=panel_pivot)
+                         panel_pivot=panel_pivot, diagonalize=diagonalize)
     dev = A.device
     tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
     T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
@@ -232,12 +239,19 @@ def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain",
     work = ws.get(sizes[3], dev)
     factor_into(F, jp, tau, T, S, work, block=block, oversample=oversample, rank=kk, pivot=pivot,
                 precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, G=G, info=info,
-                power=power, panel_pivot=panel_pivot)
-    return Factorization(F, jp, tau, T, S, int(block), kk, pivot)
+                power=power, panel_pivot=panel_pivot, diagonalize=diagonalize)
+    return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize))
+
+
+def _plain(Fz):
+    if Fz.diagonalized:
+        raise RqrcpError(4, "Q and P of a diagonalised factorization carry U' and V' (rqrcp_apply_q, "
+                            "rqrcp_apply_p and rqrcp_lowrank cover factorizations without them)")
 
 
 def apply_q(Fz: Factorization, C, trans=False):
     """Q C or Q^T C in place on a column-major C; returns C."""
+    _plain(Fz)
     L = load_library()
     m, k = Fz.F.shape[0], Fz.rank
     dt = _dt(C)
@@ -251,6 +265,7 @@ def apply_q(Fz: Factorization, C, trans=False):
 
 def apply_p(Fz: Factorization, C, trans=False):
     """C P or C P^T in place on a column-major C (nrow x n); returns C."""
+    _plain(Fz)
     L = load_library()
     n, k = Fz.F.shape[1], Fz.rank
     dt = _dt(C)
@@ -264,6 +279,7 @@ def apply_p(Fz: Factorization, C, trans=False):
 
 def lowrank(Fz: Factorization, k=None):
     """A_k = Q(:, 0:k) R(0:k, :) P^* as a new column-major tensor."""
+    _plain(Fz)
     L = load_library()
     m, n = Fz.F.shape
     k = Fz.rank if k is None else int(k)
@@ -279,6 +295,7 @@ def lowrank(Fz: Factorization, k=None):
 
 def lowrank_backward(A, Fz: Factorization, dAk, k=None):
     """Gradient w.r.t. A of a loss of A_k, pivots held fixed (column-major in/out)."""
+    _plain(Fz)
     L = load_library()
     m, n = A.shape
     k = Fz.rank if k is None else int(k)

@@ -93,6 +93,7 @@ struct FactorPlan {
   bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
   int power = 0;   // steps of the power iteration on every sketched block
   bool panel_pivot = false;   // in-block pivot P-hat by QRCP of the panel's R'
+  bool diag = false;          // diagonalised blocks (Section 6.2)
   // FP32-storage buffers
   size_t Pw = 0, V32 = 0, VT32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
   int nslots = 0;
@@ -137,6 +138,11 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->power > 0 && dt != RQRCP_F64 && !o->fixed_pivots)
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only in this build");
   if (o->panel_pivot != 0 && o->panel_pivot != 1) return fail(h, RQRCP_ERR_ARG, "opts.panel_pivot must be 0 or 1");
+  if (o->diagonalize != 0 && o->diagonalize != 1) return fail(h, RQRCP_ERR_ARG, "opts.diagonalize must be 0 or 1");
+  if (o->diagonalize && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_ORTHO))
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: FP64 storage and orthonormal pivoting only");
+  if (o->diagonalize && o->block > svd_small_max_block())
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 64 in this build");
   if (o->panel_pivot && !o->fixed_pivots && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_PERM))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: FP64 storage and the permutation form only");
   FactorPlan P;
@@ -150,6 +156,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.fixed = o->fixed_pivots != 0;
   P.power = P.fixed ? 0 : o->power;
   P.panel_pivot = !P.fixed && o->panel_pivot != 0;
+  P.diag = o->diagonalize != 0;
   P.classical_tail = !P.ortho && !P.fixed && o->tail == RQRCP_TAIL_CLASSICAL && P.k == n;
   if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
   if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
@@ -205,10 +212,11 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
       }
     }
     gpart = std::max(gpart, gemm_part_doubles(mi, bi, bi));
+    if (P.diag) gpart = std::max(gpart, gemm_part_doubles(r0, bi, bi));   // A12 V'
     if (ni > bi) {
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, mi));
       gpart = std::max(gpart, gemm_part_doubles(mi, ni - bi, bi));
-      gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));   // T^T W
+      gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));   // T^T W and U'^T C
       gpart32 = std::max(gpart32, gemm_part_doubles(bi, ni - bi, mi));
       gpart32 = std::max(gpart32, gemm_part_doubles(mi, ni - bi, bi));
     }
@@ -470,7 +478,7 @@ rqrcp_status_t rqrcp_factor_sizes(rqrcp_dtype_t dt, int64_t m, int64_t n, const 
   if (S_elems) {
     size_t vs = 0;
     for (int64_t i = 0; i < P.nblocks; ++i) vs += (size_t)(n - i * P.b) * P.b;
-    *S_elems = P.ortho ? vs + (size_t)P.nblocks * P.b + (size_t)P.nblocks * P.b * P.b : 0;
+    *S_elems = P.ortho ? vs + (size_t)P.nblocks * P.b + (size_t)P.nblocks * P.b * P.b * (P.diag ? 3 : 1) : 0;
   }
   if (work_bytes) *work_bytes = P.total;
   return RQRCP_OK;
@@ -542,11 +550,14 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   }
   double *tauS = P.ortho ? S + vs_total : nullptr;
   double *TS = P.ortho ? tauS + P.nblocks * b : nullptr;
+  double *UVd = P.diag ? TS + (size_t)P.nblocks * b * b : nullptr;   // U'_i, V'_i per block
 
   CHK(launch_zero_u32(s, bars, (size_t)P.nslots * kSlotWords), "zero barrier state");
   CHK(launch_zero_u32(s, Tout, (size_t)P.nblocks * b * b * 2), "zero T");
   if (info) CHK(launch_zero_u32(s, info, 4), "zero info");
-  if (P.ortho) CHK(launch_zero_u32(s, S, (vs_total + P.nblocks * b + (size_t)P.nblocks * b * b) * 2), "zero S");
+  if (P.ortho)
+    CHK(launch_zero_u32(s, S, (vs_total + P.nblocks * b + (size_t)P.nblocks * b * b * (P.diag ? 3 : 1)) * 2),
+        "zero S");
   if (P.fixed) {
     T *Ac = at<T>(work, P.Acopy);
     CHK(launch_copy2d_t(s, A, lda, Ac, m, m, n), "copy A");
@@ -865,6 +876,25 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
           CHK(launch_gemm<float>(s, gu, gpart32), "C -= (V T^T) W");
         }
+      }
+    }
+    // Section 6.2: R22 = U' D V'^T; U-tilde = Q-tilde diag(U', I) puts U'^T on
+    // the block's rows right of it, V' multiplies its columns above it, and
+    // the triangle becomes D (orthonormal pivoting, FP64, serial schedule)
+    if constexpr (!F32) if (P.diag) {
+      double *Ud = UVd + (size_t)i * 2 * b * b, *Vd = Ud + (size_t)b * b;
+      ScopedTimer td(h, RQRCP_K_TFACTOR, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
+                     16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi);
+      CHK(launch_svd_small(s, X, lda, (int)bi, Ud, b, Vd, b), "SVD of the block's triangle");
+      if (ni > bi) {
+        GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
+        CHK(launch_gemm_f64(s, gu, gpart), "U'^T times the block's rows");
+        CHK(launch_copy2d(s, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
+      }
+      if (r0 > 0) {
+        GemmF64 gv{false, false, r0, bi, bi, A + r0 * lda, lda, Vd, b, Vt, r0, 1.0, 0.0};
+        CHK(launch_gemm_f64(s, gv, gpart), "columns above the block times V'");
+        CHK(launch_copy2d(s, Vt, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
       }
     }
   }

@@ -282,4 +282,11 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p);
 // T of the compact WY form from tau and the Gram matrix S = V^T V.
 hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt);
 
+// SVD of the nb x nb upper triangle of F (ld ldf, nb <= svd_small_max_block()):
+// R22 = U' D V'^T with D decreasing, written as U (nb x nb, ld ldu), V (ld ldv)
+// and D on the diagonal of F, whose strict upper triangle is cleared.
+int svd_small_max_block();
+hipError_t launch_svd_small(hipStream_t s, double *F, int64_t ldf, int nb, double *U, int64_t ldu, double *V,
+                            int64_t ldv);
+
 }  // namespace rq

@@ -52,7 +52,7 @@ def test_default_options_and_status_strings(lib):
     o = R.Opts()
     lib.rqrcp_default_opts(ctypes.byref(o))
     assert (o.block, o.oversample, o.rank, o.pivot, o.precision, o.tail, o.fixed_pivots) == (128, 10, 0, 0, 0, 0, 0)
-    assert o.seed == 0 and not o.G and not o.info and o.power == 0 and o.panel_pivot == 0
+    assert o.seed == 0 and not o.G and not o.info and o.power == 0 and o.panel_pivot == 0 and o.diagonalize == 0
     for st in range(6):
         assert lib.rqrcp_status_string(st)
 
@@ -80,6 +80,8 @@ def test_factor_sizes_follow_the_block_structure(lib):
     (100, 100, {"power": -1}, ERR_ARG),                     # q < 0
     (100, 100, {"power": 9}, ERR_ARG),                      # q > 8
     (100, 100, {"pivot": "ortho", "panel_pivot": True}, ERR_UNSUPPORTED),  # P-hat: permutation form only
+    (100, 100, {"diagonalize": True}, ERR_UNSUPPORTED),     # Section 6.2 blocks: orthonormal pivoting only
+    (100, 100, {"pivot": "ortho", "diagonalize": True, "block": 65}, ERR_UNSUPPORTED),   # b <= 64
 ])
 def test_factor_sizes_rejects_invalid_arguments(lib, m, n, kw, status):
     o = R.make_opts(**kw)
@@ -98,6 +100,12 @@ def test_power_iteration_and_panel_pivoting_need_fp64_storage(lib):
     # P-hat needs FP64 storage as well
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == ERR_UNSUPPORTED
     assert lib.rqrcp_factor_sizes(0, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == 0
+    # diagonalised blocks: FP64, and S grows by U'_i, V'_i (b x b each) per block
+    o = R.make_opts(pivot="ortho", diagonalize=True, block=32)
+    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(o), *args) == ERR_UNSUPPORTED
+    _, _, s0, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32)
+    _, _, s1, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32, diagonalize=True)
+    assert s1 - s0 == 2 * 13 * 32 * 32
     # fixed pivots draw no sketch: the power setting is ignored
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1, fixed_pivots=True)), *args) == 0
 
