@@ -482,14 +482,15 @@ def test_panel_pairs_fallbacks_and_zero_columns():
     assert taus[9] == 0.0 and Rg[9, 9] == 0.0
 
 
-@pytest.mark.parametrize("m,n,b", [(640, 512, 64), (1024, 1024, 128)])
-def test_fixed_pivot_refactorization_repeats_the_forward(m, n, b):
+@pytest.mark.parametrize("m,n,b,phat", [(640, 512, 64, False), (1024, 1024, 128, False), (640, 512, 64, True)])
+def test_fixed_pivot_refactorization_repeats_the_forward(m, n, b, phat):
     """The forward (overlapped schedule: next sketch and update on the
     auxiliary stream) and a fixed-pivot refactorization (serial schedule, no
     sketch) apply the same operations to the panel and trailing columns, so
-    R, the reflectors, tau and T agree bit for bit."""
+    R, the reflectors, tau and T agree bit for bit.  With the in-block pivot
+    P-hat the forward factors the restored, permuted panel: the same bits."""
     A = W.make_matrix(m, n, W.sigma_geometric(n, 6.0), seed=m + b).to(DEV)
-    Fz = R.factor(A, block=b, oversample=8, seed=4)
+    Fz = R.factor(A, block=b, oversample=8, seed=4, panel_pivot=phat)
     Fx = R.factor(A, block=b, oversample=8, seed=4, jpvt=Fz.jpvt)
     torch.cuda.synchronize()
     assert torch.equal(Fx.jpvt, Fz.jpvt)
