@@ -3,7 +3,9 @@
 // panel (b <= 64).  One workgroup holds the working matrix and V' in LDS and
 // runs one-sided Jacobi (Hestenes): every sweep visits each column pair once,
 // in the round-robin order that splits a sweep into b - 1 rounds of b/2
-// disjoint pairs, and rotates the pair until it is orthogonal.  At
+// disjoint pairs, and rotates the pair until it is orthogonal.  The squared
+// column norms are computed at the start of a sweep and carried through each
+// rotation (a' = a - t g, b' = b + t g), so a pair needs one reduction.  At
 // convergence the columns are U' D; D is sorted in decreasing order (the
 // order of the reference SVD), U' = columns / D, and columns whose singular
 // value is at rounding level are replaced by an orthonormal completion.
@@ -24,6 +26,7 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
   __shared__ double a[kSvdMaxB][kSvdMaxB + 1];   // a[column][row]
   __shared__ double v[kSvdMaxB][kSvdMaxB + 1];
   __shared__ double sig[kSvdMaxB];
+  __shared__ double nrm[kSvdMaxB];   // squared column norms within a sweep
   __shared__ int order[kSvdMaxB];
   __shared__ int rotated;
   const int t = threadIdx.x;
@@ -34,10 +37,16 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
     a[c][r] = (c < n && r < n && r <= c) ? F[r + (int64_t)c * ldf] : 0.0;
     v[c][r] = c == r ? 1.0 : 0.0;
   }
+  __syncthreads();   // the sweep's norms read columns loaded by other threads
   const int g = t / kSvdGroup, l = t % kSvdGroup;
   const double tol = (double)n * 2.220446049250313e-16;
   for (int sweep = 0; sweep < kSvdMaxSweeps; ++sweep) {
     if (t == 0) rotated = 0;
+    if (t < kSvdMaxB) {
+      double s2 = 0.0;
+      for (int r = 0; r < n; ++r) s2 += a[t][r] * a[t][r];
+      nrm[t] = s2;
+    }
     __syncthreads();
     for (int k = 0; k + 1 < ne; ++k) {
       // round k of the circle method: (k, ne-1) and ((k+j), (k-j)) mod (ne-1)
@@ -46,18 +55,12 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
         int p = g == 0 ? k : (k + g) % m1;
         int q = g == 0 ? m1 : (k - g + m1) % m1;
         if (p > q) { const int x = p; p = q; q = x; }
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = l; r < n; r += kSvdGroup) {
-          const double x = a[p][r], y = a[q][r];
-          al += x * x; be += y * y; ga += x * y;
-        }
+        const double al = nrm[p], be = nrm[q];
+        double ga = 0.0;
+        for (int r = l; r < n; r += kSvdGroup) ga += a[p][r] * a[q][r];
 #pragma unroll
-        for (int o = 1; o < kSvdGroup; o <<= 1) {
-          al += __shfl_xor(al, o, kSvdGroup);
-          be += __shfl_xor(be, o, kSvdGroup);
-          ga += __shfl_xor(ga, o, kSvdGroup);
-        }
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        for (int o = 1; o < kSvdGroup; o <<= 1) ga += __shfl_xor(ga, o, kSvdGroup);
+        if (ga * ga > tol * tol * al * be) {
           const double zeta = (be - al) / (2.0 * ga);
           const double az = fabs(zeta);
           const double root = az > 1.0 ? az * sqrt(1.0 + 1.0 / (zeta * zeta)) : sqrt(1.0 + zeta * zeta);
@@ -71,7 +74,11 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
             v[p][r] = cs * vx - sn * vy;
             v[q][r] = sn * vx + cs * vy;
           }
-          if (l == 0) rotated = 1;
+          if (l == 0) {
+            nrm[p] = al - tn * ga;
+            nrm[q] = be + tn * ga;
+            rotated = 1;
+          }
         }
       }
       __syncthreads();
