@@ -109,3 +109,30 @@ def test_gpu_method_3_diagonal_tracks_the_singular_values(name, make):
     d = np.diag(Fz.F.cpu().numpy())
     assert np.median(np.abs(np.log(d / s))) <= 0.05
     assert S7.summary(e_gpu, A)["to_svd_geomean"] <= 1.02
+
+
+@pytest.mark.parametrize("rank_a", [0, 20])
+def test_diagonalised_blocks_of_rank_deficient_inputs(rank_a):
+    """Exact rank 20 (the rank falls inside the second block) and the zero
+    matrix: the triangles past the rank have singular values at rounding
+    level, whose U' columns the kernel completes to an orthonormal basis."""
+    m, n, b = 120, 96, 16
+    progress(f"blockRRQR rank-deficient rank={rank_a}")
+    if rank_a:
+        A = W.make_matrix(m, n, W.sigma_rank(n, rank_a), seed=7).numpy()
+    else:
+        A = np.zeros((m, n))
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=8, seed=3, pivot="ortho", power=1,
+                  diagonalize=True)
+    torch.cuda.synchronize()
+    ref = O.rqrcp(A, b, 8, seed=3, pivot="ortho", power=1, diagonalize=True)
+    nA = max(np.linalg.norm(A), 1.0)
+    d = np.diag(Fz.F.cpu().numpy())
+    assert np.max(np.abs(d - np.diag(ref["F"]))) <= 1e-9 * nA
+    assert np.all(d[max(rank_a, 0):] <= 1e-12 * nA)
+    res = _as_result(Fz, m, n, b)
+    Q, P = O.form_q(res, m), O.form_p(res)
+    Rg = np.triu(res["F"])
+    assert np.linalg.norm(Q.T @ A @ P - Rg) / nA <= 1e-13
+    assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 1e-12
+    assert np.linalg.norm(P.T @ P - np.eye(n)) <= 1e-12
