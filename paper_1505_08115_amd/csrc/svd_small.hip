@@ -56,8 +56,19 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
         int q = g == 0 ? m1 : (k - g + m1) % m1;
         if (p > q) { const int x = p; p = q; q = x; }
         const double al = nrm[p], be = nrm[q];
+        // the pair's rows of this lane, read once (rows past n read as zero:
+        // the padding rows of a and v hold zeros and are never written)
+        constexpr int kRows = kSvdMaxB / kSvdGroup;
+        double xp[kRows], xq[kRows], yp[kRows], yq[kRows];
         double ga = 0.0;
-        for (int r = l; r < n; r += kSvdGroup) ga += a[p][r] * a[q][r];
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+          const int r = l + j * kSvdGroup;
+          xp[j] = a[p][r]; xq[j] = a[q][r];
+          yp[j] = v[p][r]; yq[j] = v[q][r];
+        }
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) ga += xp[j] * xq[j];
 #pragma unroll
         for (int o = 1; o < kSvdGroup; o <<= 1) ga += __shfl_xor(ga, o, kSvdGroup);
         if (ga * ga > tol * tol * al * be) {
@@ -66,13 +77,15 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
           const double root = az > 1.0 ? az * sqrt(1.0 + 1.0 / (zeta * zeta)) : sqrt(1.0 + zeta * zeta);
           const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
           const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
-          for (int r = l; r < n; r += kSvdGroup) {
-            const double x = a[p][r], y = a[q][r];
-            a[p][r] = cs * x - sn * y;
-            a[q][r] = sn * x + cs * y;
-            const double vx = v[p][r], vy = v[q][r];
-            v[p][r] = cs * vx - sn * vy;
-            v[q][r] = sn * vx + cs * vy;
+#pragma unroll
+          for (int j = 0; j < kRows; ++j) {
+            const int r = l + j * kSvdGroup;
+            if (r < n) {
+              a[p][r] = cs * xp[j] - sn * xq[j];
+              a[q][r] = sn * xp[j] + cs * xq[j];
+              v[p][r] = cs * yp[j] - sn * yq[j];
+              v[q][r] = sn * yp[j] + cs * yq[j];
+            }
           }
           if (l == 0) {
             nrm[p] = al - tn * ga;
