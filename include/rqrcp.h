@@ -250,7 +250,7 @@ typedef enum {
   RQRCP_K_W_GEMM = 7,      /* W = V^T C                                       */
   RQRCP_K_UPDATE_GEMM = 8, /* C -= V (T^T W) (FP64), (V T^T) W (FP32)         */
   RQRCP_K_ORTHO = 9,       /* QR of the sketch and right-application of S_i   */
-  RQRCP_K_OTHER = 10,
+  RQRCP_K_OTHER = 10,      /* the diagonalised blocks (SVD and rotations)     */
   RQRCP_K_COUNT = 11
 } rqrcp_kernel_class_t;
 rqrcp_status_t rqrcp_timing_enable(rqrcp_handle_t h, int enable);

@@ -883,7 +883,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     // the triangle becomes D (orthonormal pivoting, FP64, serial schedule)
     if constexpr (!F32) if (P.diag) {
       double *Ud = UVd + (size_t)i * 2 * b * b, *Vd = Ud + (size_t)b * b;
-      ScopedTimer td(h, RQRCP_K_TFACTOR, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
+      ScopedTimer td(h, RQRCP_K_OTHER, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
                      16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi);
       CHK(launch_svd_small(s, X, lda, (int)bi, Ud, b, Vd, b), "SVD of the block's triangle");
       if (ni > bi) {
