@@ -29,6 +29,7 @@ struct rqrcp_ctx {
   hipStream_t aux = nullptr;
   int ncu = 0;
   hipEvent_t ev_moves = nullptr, ev_ypre = nullptr, ev_vt = nullptr, ev_upd = nullptr, ev_w = nullptr;
+  hipEvent_t ev_diag = nullptr;   // the diagonalised block's work on the side stream
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
@@ -171,6 +172,10 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     if (pn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "panel too large for the panel kernel");
     ppart = std::max(ppart, panel_part_doubles(pn, (int)bi));
     vtp = std::max(vtp, gemm_part_doubles(mi, bi, bi));
+    if (P.diag) {   // U'^T C and A12 V' run on the side stream as well
+      vtp = std::max(vtp, gemm_part_doubles(bi, ni - bi, bi));
+      vtp = std::max(vtp, gemm_part_doubles(r0, bi, bi));
+    }
     if (!P.fixed) {
       if (block_is_classical_tail(P, i)) {
         int cpw = 0;
@@ -391,7 +396,7 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-  hipEvent_t *evs[5] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd, &c->ev_w};
+  hipEvent_t *evs[6] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd, &c->ev_w, &c->ev_diag};
   for (hipEvent_t *ev : evs)
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -424,7 +429,7 @@ rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
   for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
-  for (hipEvent_t e : {h->ev_moves, h->ev_ypre, h->ev_vt, h->ev_upd, h->ev_w})
+  for (hipEvent_t e : {h->ev_moves, h->ev_ypre, h->ev_vt, h->ev_upd, h->ev_w, h->ev_diag})
     if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -603,6 +608,14 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     upd_pending = false;
     return hipStreamWaitEvent(s, h->ev_upd, 0);
   };
+  // the previous block's diagonalisation runs on the side stream beside this
+  // block's sketch and its QR; it must end before S_i touches the rows above
+  bool diag_pending = false;
+  auto join_diag = [&]() -> hipError_t {
+    if (!diag_pending) return hipSuccess;
+    diag_pending = false;
+    return hipStreamWaitEvent(s, h->ev_diag, 0);
+  };
 
   for (int64_t i = 0; i < P.nblocks; ++i) {
     const int64_t r0 = i * b, bi = std::min(b, P.k - r0), mi = m - r0, ni = n - r0;
@@ -689,6 +702,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_panel_qr(s, pq), "QR of the sketch");
           CHK(launch_wy_t(s, (int)bi, tauS + i * b, Sg, TSi, b), "T of the sketch reflectors");
           // A(0:m, r0:n) <- A(0:m, r0:n) (I - VS TS VS^T), all m rows
+          CHK(join_diag(), "wait for the previous block's diagonalisation");
           T *Ac = A + r0 * lda;
           if constexpr (!F32) {
             GemmF64 g1{false, false, m, bi, ni, Ac, lda, VS, ni, Vb, m, 1.0, 0.0};
@@ -880,24 +894,35 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     }
     // Section 6.2: R22 = U' D V'^T; U-tilde = Q-tilde diag(U', I) puts U'^T on
     // the block's rows right of it, V' multiplies its columns above it, and
-    // the triangle becomes D (orthonormal pivoting, FP64, serial schedule)
+    // the triangle becomes D (orthonormal pivoting, FP64).  None of it is read
+    // by the next block's sketch, power steps or QR of the sketch (rows and
+    // columns past this block; their own buffers), so it runs on the side
+    // stream (one workgroup for the SVD) beside them
     if constexpr (!F32) if (P.diag) {
       double *Ud = UVd + (size_t)i * 2 * b * b, *Vd = Ud + (size_t)b * b;
-      ScopedTimer td(h, RQRCP_K_OTHER, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
-                     16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi);
-      CHK(launch_svd_small(s, X, lda, (int)bi, Ud, b, Vd, b), "SVD of the block's triangle");
-      if (ni > bi) {
-        GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
-        CHK(launch_gemm_f64(s, gu, gpart), "U'^T times the block's rows");
-        CHK(launch_copy2d(s, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
+      hipStream_t sd = h->side;
+      CHK(hipEventRecord(h->fork_ev, s), "fork event");
+      CHK(hipStreamWaitEvent(sd, h->fork_ev, 0), "side stream wait");
+      {
+        ScopedTimer td(h, RQRCP_K_OTHER, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
+                       16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi, sd);
+        CHK(launch_svd_small(sd, X, lda, (int)bi, Ud, b, Vd, b), "SVD of the block's triangle");
+        if (ni > bi) {
+          GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
+          CHK(launch_gemm_f64(sd, gu, vtpart), "U'^T times the block's rows");
+          CHK(launch_copy2d(sd, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
+        }
+        if (r0 > 0) {
+          GemmF64 gv{false, false, r0, bi, bi, A + r0 * lda, lda, Vd, b, Vt, r0, 1.0, 0.0};
+          CHK(launch_gemm_f64(sd, gv, vtpart), "columns above the block times V'");
+          CHK(launch_copy2d(sd, Vt, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
+        }
       }
-      if (r0 > 0) {
-        GemmF64 gv{false, false, r0, bi, bi, A + r0 * lda, lda, Vd, b, Vt, r0, 1.0, 0.0};
-        CHK(launch_gemm_f64(s, gv, gpart), "columns above the block times V'");
-        CHK(launch_copy2d(s, Vt, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
-      }
+      CHK(hipEventRecord(h->ev_diag, sd), "diagonalisation event");
+      diag_pending = true;
     }
   }
+  CHK(join_diag(), "wait for the last diagonalisation");
   CHK(join_update(), "wait for the trailing update");
   (void)piv;
   return RQRCP_OK;

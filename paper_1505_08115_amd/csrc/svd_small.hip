@@ -7,7 +7,7 @@
 // column norms are computed at the start of a sweep and carried through each
 // rotation (a' = a - t g, b' = b + t g), so a pair needs one reduction.  At
 // convergence the columns are U' D; D is sorted in decreasing order (the
-// order of the reference SVD), U' = columns / D, and columns whose singular
+// usual convention of the SVD), U' = columns / D, and columns whose singular
 // value is at rounding level are replaced by an orthonormal completion.
 #include "common.h"
 
