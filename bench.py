@@ -194,8 +194,8 @@ def methods_123(reps=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU execution is design-only "
-                                   "(see DESIGN.md), run with --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; multi-GPU execution is not implemented, "
+                                   "run with --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch

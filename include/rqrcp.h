@@ -66,7 +66,7 @@ typedef enum {
   RQRCP_ERR_ARG = 1,         /* invalid argument (see rqrcp_last_error)       */
   RQRCP_ERR_WORKSPACE = 2,   /* workspace missing or smaller than required    */
   RQRCP_ERR_HIP = 3,         /* a HIP runtime call or launch failed           */
-  RQRCP_ERR_UNSUPPORTED = 4, /* valid but outside what this build supports    */
+  RQRCP_ERR_UNSUPPORTED = 4, /* valid but outside what the library supports  */
   RQRCP_ERR_NONFINITE = 5    /* reserved for host-side reporting of info[0]   */
 } rqrcp_status_t;
 
@@ -159,7 +159,7 @@ rqrcp_status_t rqrcp_factor_sizes(rqrcp_dtype_t dt, int64_t m, int64_t n, const 
  * sketch, BF16 MFMA with FP32 accumulation (MIXED).
  * Errors: RQRCP_ERR_ARG (NULL pointers, m < n, n < 1, lda < m, b < 1, p < 0,
  * k > n, MIXED with F64, S given for PERM or missing for ORTHO),
- * RQRCP_ERR_WORKSPACE, RQRCP_ERR_UNSUPPORTED (sizes beyond this build's
+ * RQRCP_ERR_WORKSPACE, RQRCP_ERR_UNSUPPORTED (sizes beyond the library's
  * limits, e.g. b + p > 512 or fixed_pivots with ORTHO), RQRCP_ERR_HIP. */
 rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n,
                             void *A, int64_t lda, int32_t *jpvt, double *tau, double *T,

@@ -137,13 +137,13 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.fixed_pivots applies to the permutation form only");
   if (o->power < 0 || o->power > 8) return fail(h, RQRCP_ERR_ARG, "opts.power must be in [0, 8]");
   if (o->power > 0 && dt != RQRCP_F64 && !o->fixed_pivots)
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only in this build");
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only");
   if (o->panel_pivot != 0 && o->panel_pivot != 1) return fail(h, RQRCP_ERR_ARG, "opts.panel_pivot must be 0 or 1");
   if (o->diagonalize != 0 && o->diagonalize != 1) return fail(h, RQRCP_ERR_ARG, "opts.diagonalize must be 0 or 1");
   if (o->diagonalize && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_ORTHO))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: FP64 storage and orthonormal pivoting only");
   if (o->diagonalize && o->block > svd_small_max_block())
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 64 in this build");
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 64");
   if (o->panel_pivot && !o->fixed_pivots && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_PERM))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: FP64 storage and the permutation form only");
   FactorPlan P;
@@ -159,8 +159,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.panel_pivot = !P.fixed && o->panel_pivot != 0;
   P.diag = o->diagonalize != 0;
   P.classical_tail = !P.ortho && !P.fixed && o->tail == RQRCP_TAIL_CLASSICAL && P.k == n;
-  if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512 in this build");
-  if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512 in this build");
+  if (P.b > 512) return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.block: at most 512");
+  if (P.ks > 512 && !P.fixed) return fail(h, RQRCP_ERR_UNSUPPORTED, "block + oversample: at most 512");
 
   size_t Yd = 0, gpart = 0, ppart = 0, gpart32 = 0, spart = 0, vtp = 0;
   int qnwg = 0;
@@ -1293,7 +1293,7 @@ rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
-  if (k > 8192) return fail(h, RQRCP_ERR_UNSUPPORTED, "k: at most 8192 in the backward of this build");
+  if (k > 8192) return fail(h, RQRCP_ERR_UNSUPPORTED, "k: at most 8192 in the backward");
   if (!Av || !VR || !jpvt || !T || !dAkv || !dAv) return fail(h, RQRCP_ERR_ARG, "a required pointer is NULL");
   if (lda < m || ldvr < m || ldg < m || ldda < m) return fail(h, RQRCP_ERR_ARG, "leading dimensions must be >= m");
   if (!work || work_bytes < rqrcp_lowrank_backward_work_bytes(dt, m, n, k, b))
