@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-residual", action="store_true", help="skip the residual check (profiling)")
     ap.add_argument("--cpu-blocks", type=int, default=2, help="oracle sample: leading blocks factored on the CPU")
     ap.add_argument("--no-bwd", action="store_true", help="skip the bwd/fwd ratio measurement (C5)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the C4 (16384 x 8192) mixed vs FP64 timing")
     ap.add_argument("--power", type=int, default=1,
                     help="also time the workload with this many power-iteration steps (Section 6.3); 0 skips")
     ap.add_argument("--no-panel-pivot", action="store_true",
@@ -48,7 +49,9 @@ def parse():
 
 
 GEMM_SOURCES = ("paper_1505_08115_amd/csrc/gemm.hip",)   # the file that defines the GEMM kernels
-PMC_SUMMARY = "profiles/w_gemm_H1_pmc.txt"
+PMC_SUMMARY = "profiles/trailing_update_H1_pmc.txt"
+# the trailing update of a block (Section 5.1): T^T W, W = V^T C, C -= V (T^T W)
+UPDATE_CLASSES = ("vt_gemm", "w_gemm", "update_gemm")
 
 
 def gemm_source_hash():
@@ -61,7 +64,7 @@ def gemm_source_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per W = V^T C launch from the committed counter summary,
+    """HBM bytes per block's trailing update from the committed counter summary,
     or None when there is none for this workload or the GEMM sources have
     changed since the counters were taken."""
     path = os.path.join(ROOT, PMC_SUMMARY)
@@ -209,34 +212,37 @@ def main():
     A = W.workload_matrix(w, device=dev)
     m, n = A.shape
 
-    def run(wl, Ain, steps, warmup, profile, check=True, power=0, panel_pivot=False):
+    def run(wl, Ain, steps, warmup, profile, check=True, power=0, panel_pivot=False, fixed=None):
         """Time `steps` factorizations of Ain (already resident) with HIP events.
 
-        Inside the timed steps only the W = V^T C and trailing-update launches
-        are bracketed by the library's events (the roofline and the overlapped
-        update are measured live); with `profile`, `steps` further
+        Inside the timed steps only the launches of the trailing update (T^T W,
+        W = V^T C, the update) are bracketed by the library's events (the
+        roofline is measured live); with `profile`, `steps` further
         factorizations bracket every kernel class for the breakdown, outside
-        the timed region."""
+        the timed region.  fixed: a jpvt to refactor with (fixed pivots, no
+        sketch; the blocks run one after the other)."""
         dtype = torch.float32 if wl.precision == "mixed" else torch.float64
+        m, n = Ain.shape
         A0 = R.colmajor(Ain.to(dtype))
         F = torch.empty_like(A0)
         sizes = R.factor_sizes(m, n, dtype, block=wl.b, oversample=wl.p, pivot=wl.pivot, rank=wl.rank,
                                precision="mixed" if wl.precision == "mixed" else "plain", power=power,
-                               panel_pivot=panel_pivot)
-        jp = torch.empty(n, dtype=torch.int32, device=dev)
+                               panel_pivot=panel_pivot, fixed_pivots=fixed is not None)
+        jp = torch.empty(n, dtype=torch.int32, device=dev) if fixed is None else fixed.clone()
         tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
         T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
         S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if wl.pivot == "ortho" else None
         work = torch.empty(sizes[3], dtype=torch.uint8, device=dev)
         info = torch.zeros(4, dtype=torch.int32, device=dev)
         kw = dict(block=wl.b, oversample=wl.p, seed=wl.seed, pivot=wl.pivot, rank=wl.rank, info=info,
-                  precision="mixed" if wl.precision == "mixed" else "plain", power=power, panel_pivot=panel_pivot)
+                  precision="mixed" if wl.precision == "mixed" else "plain", power=power, panel_pivot=panel_pivot,
+                  fixed_pivots=fixed is not None)
         for _ in range(warmup):
             F.copy_(A0)
             R.factor_into(F, jp, tau, T, S, work, **kw)
         torch.cuda.synchronize()
         if profile:
-            R.timing_classes(["w_gemm", "update_gemm"])
+            R.timing_classes(list(UPDATE_CLASSES))
             R.timing_enable(True)
             R.timing_read()
         times = []
@@ -260,6 +266,7 @@ def main():
             every = R.timing_read()
         R.timing_enable(False)
         prof = (prof, every)
+        run.last_jpvt = jp.clone()
         if not check:
             return times, prof, None, info.tolist()
         # correctness of the timed factorization, against the matrix it saw;
@@ -267,12 +274,13 @@ def main():
         Ad = A0.double()
         Fd = F.double()
         Q = torch.linalg.householder_product(Fd.contiguous(), tau.contiguous())
-        res = float(torch.linalg.norm(Ad[:, jp.long()] - Q @ torch.triu(Fd)) / torch.linalg.norm(Ad)) \
+        res = float(torch.linalg.norm(Ad[:, jp.long()] - Q @ torch.triu(Fd[:n])) / torch.linalg.norm(Ad)) \
             if wl.pivot == "perm" else None
         del Q, Fd, Ad, work
         return times, prof, res, info.tolist()
 
     times, (prof, prof_all), res, info = run(w, A, args.steps, args.warmup, True, check=not args.no_residual)
+    jp_main = run.last_jpvt
     ms = float(np.mean(times))
     flops = W.flops_normalised(m, n)
     value = flops / (ms * 1e-3) / 1e9
@@ -289,6 +297,27 @@ def main():
                  "value": flops / (mms * 1e-3) / 1e9, "ms_per_step": mms, "residual": mres, "info": minfo,
                  "speedup_vs_fp64": ms / mms,
                  "breakdown": {k: v[1] / args.steps for k, v in mprof.items()}}
+
+    # C4: the tall mixed-precision workload (16384 x 8192, FP32 storage, BF16
+    # sketch, b = 256, p = 16) beside the plain FP64 factorization of the same
+    # matrix with the same block sizes
+    c4 = None
+    if w.name == "H1" and not args.no_c4:
+        w4 = W.WORKLOADS["C4"]
+        A4 = W.workload_matrix(w4, device=dev)
+        f4 = W.flops_normalised(w4.m, w4.n)
+        t4m, (_, p4m), r4m, i4m = run(w4, A4, args.steps, args.warmup, True, check=not args.no_residual)
+        w4p = W.Workload("C4 plain", w4.m, w4.n, w4.b, w4.p, "perm", "f64", w4.profile, w4.seed)
+        t4p, (_, p4p), r4p, i4p = run(w4p, A4, args.steps, args.warmup, True, check=not args.no_residual)
+        del A4
+        m4, p4 = float(np.mean(t4m)), float(np.mean(t4p))
+        c4 = {"workload": f"C4: {w4.m}x{w4.n}, b={w4.b}, p={w4.p}; mixed (FP32 storage, BF16 sketch, FP32 update) "
+                          f"and plain FP64 on the same matrix",
+              "mixed": {"ms_per_step": m4, "value": f4 / (m4 * 1e-3) / 1e9, "residual": r4m, "info": i4m,
+                        "breakdown": {k: v[1] / args.steps for k, v in p4m.items()}},
+              "fp64": {"ms_per_step": p4, "value": f4 / (p4 * 1e-3) / 1e9, "residual": r4p, "info": i4p,
+                       "breakdown": {k: v[1] / args.steps for k, v in p4p.items()}},
+              "speedup_mixed_vs_fp64": p4 / m4}
 
     # the same factorization with q steps of the power iteration on every
     # sketch (Section 6.3): two more products per block, serial schedule
@@ -313,21 +342,46 @@ def main():
                 "value": flops / (hms * 1e-3) / 1e9, "slowdown_vs_identity": hms / ms, "residual": hres,
                 "info": hinfo, "breakdown": {k: v[1] / args.steps for k, v in hprof.items()}}
 
-    # roofline of the dominant matrix-core kernel on the critical path: W = V^T C
-    # (the sketch product and the trailing update run on the capped auxiliary
-    # stream, overlapped with the panel and the pivoted QR; reported below)
-    nl, tms, tfl, tby = prof.get("w_gemm", (0, 0.0, 0.0, 0.0))
+    # roofline of the trailing update, the matrix-core work of every block
+    # (Section 5.1): T^T W, W = V^T C and C -= V (T^T W), measured live inside
+    # the timed steps with HIP events on the streams they run on (the update
+    # itself on the auxiliary stream, capped at half the CUs, beside the next
+    # block's pivoted QR); one "launch" = one block's three products
+    nb_upd = prof.get("w_gemm", (0,))[0]
+    tfl = sum(prof.get(c, (0, 0.0, 0.0, 0.0))[2] for c in UPDATE_CLASSES)
+    tms = sum(prof.get(c, (0, 0.0, 0.0, 0.0))[1] for c in UPDATE_CLASSES)
+    tby = sum(prof.get(c, (0, 0.0, 0.0, 0.0))[3] for c in UPDATE_CLASSES)
     achieved = tfl / (tms * 1e-3) / 1e12 if tms > 0 else 0.0
-    roof = {"kernel": "dgemm W = V^T C (all-rows kernel + fixed-order split-K sum)", "bound": "mfma",
+    parts = {}
+    for c in UPDATE_CLASSES:
+        n_, ms_, fl_, _ = prof.get(c, (0, 0.0, 0.0, 0.0))
+        parts[c] = {"avg_launch_ms": ms_ / max(1, n_), "tflops": fl_ / (ms_ * 1e-3) / 1e12 if ms_ > 0 else 0.0,
+                    "launches_per_step": n_ / max(1, args.steps)}
+    roof = {"kernel": "trailing update per block: T^T W + W = V^T C + C -= V (T^T W) (FP64 MFMA; the last "
+                      "on the auxiliary stream at half the CUs)", "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": measured_traffic(w.name), "launches_per_step": nl / max(1, args.steps),
-            "avg_launch_ms": tms / max(1, nl), "flops_per_launch": tfl / max(1, nl),
-            "algorithmic_bytes_per_launch": tby / max(1, nl)}
-    ul, ums, ufl, _ = prof.get("update_gemm", (0, 0.0, 0.0, 0.0))
-    update_overlapped = {"kernel": "dgemm C -= V (T^T W) on the auxiliary stream, grid capped at half the CUs",
-                         "avg_launch_ms": ums / max(1, ul),
-                         "achieved_tflops": ufl / (ums * 1e-3) / 1e12 if ums > 0 else 0.0,
-                         "launches_per_step": ul / max(1, args.steps)}
+            "traffic": measured_traffic(w.name), "launches_per_step": nb_upd / max(1, args.steps),
+            "avg_launch_ms": tms / max(1, nb_upd), "flops_per_launch": tfl / max(1, nb_upd),
+            "algorithmic_bytes_per_launch": tby / max(1, nb_upd), "parts": parts}
+    # the dominant kernel of the factorization: the pivoted QR of the sketch,
+    # one grid-wide exchange per pivot decision (latency-bound)
+    qn, qms, qfl, _ = prof_all.get("qrcp", (0, 0.0, 0.0, 0.0))
+    qsteps_all = sum(min(w.b, n - i * w.b) for i in range(-(-n // w.b))) if w.rank == 0 else w.rank
+    dominant = {"kernel": "qrcp_reg_kernel (pivoted QR of the sketch, Section 4.1 eq. Yrows)", "bound": "latency",
+                "achieved": qfl / (qms * 1e-3) / 1e12 if qms > 0 else 0.0, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": (qfl / (qms * 1e-3) / 1e12) / PEAK_FP64_TFLOPS if qms > 0 else 0.0,
+                "ms_per_step": qms / args.steps, "share_of_step": qms / args.steps / ms,
+                "us_per_pivot_step": qms / args.steps / qsteps_all * 1e3}
+    # the trailing update alone on the whole chip: a fixed-pivot
+    # refactorization runs the blocks one after the other, the update uncapped
+    uncapped = None
+    if w.pivot == "perm" and w.precision != "mixed":
+        _, (uprof, _), _, _ = run(w, A, args.steps, 1, True, check=False, fixed=jp_main)
+        un, ums, ufl, _ = uprof.get("update_gemm", (0, 0.0, 0.0, 0.0))
+        uncapped = {"kernel": "C -= V (T^T W) uncapped on the whole chip (fixed-pivot refactorization, "
+                              "blocks one after the other)",
+                    "avg_launch_ms": ums / max(1, un), "achieved_tflops": ufl / (ums * 1e-3) / 1e12 if ums else 0.0,
+                    "frac": (ufl / (ums * 1e-3) / 1e12) / PEAK_FP64_TFLOPS if ums else 0.0}
     # the latency-bound cooperative kernels: one grid-wide exchange per pivot
     # decision (pivoted QR of the sketch) and per panel column
     qsteps = sum(min(w.b, n - i * w.b) for i in range(-(-n // w.b))) if w.rank == 0 else w.rank
@@ -347,9 +401,10 @@ def main():
                                f"p={w.p}, {w.pivot} pivoting, A = U diag(s) V^T, Haar U,V, seed {w.seed}",
                    "m": m, "n": n, "block": w.b, "oversample": w.p, "pivot": w.pivot},
         "roofline": roof,
+        "roofline_dominant": dominant,
         "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "latency": latency,
-                  "update_overlapped": update_overlapped,
-                  "mixed": mixed, "power_iteration": power, "panel_pivot": phat},
+                  "update_uncapped": uncapped,
+                  "mixed": mixed, "c4": c4, "power_iteration": power, "panel_pivot": phat},
     }
     if not args.no_bwd:
         out["extra"]["methods_123"] = methods_123()

@@ -67,7 +67,9 @@ typedef enum {
   RQRCP_ERR_WORKSPACE = 2,   /* workspace missing or smaller than required    */
   RQRCP_ERR_HIP = 3,         /* a HIP runtime call or launch failed           */
   RQRCP_ERR_UNSUPPORTED = 4, /* valid but outside what the library supports  */
-  RQRCP_ERR_NONFINITE = 5    /* reserved for host-side reporting of info[0]   */
+  RQRCP_ERR_NONFINITE = 5,   /* info[0]: a non-finite norm (rqrcp_check)      */
+  RQRCP_ERR_TIMEOUT = 6      /* info[2]: a grid-wide wait gave up; results    */
+                             /* invalid (rqrcp_check)                         */
 } rqrcp_status_t;
 
 typedef enum { RQRCP_F64 = 0, RQRCP_F32 = 1 } rqrcp_dtype_t;               /* storage type of A   */
@@ -92,7 +94,9 @@ typedef struct {
   int32_t *info;        /* NULL, or device int32[4], zeroed by the library and set:    */
                         /* [0] = 1 if a non-finite norm was met, [1] = first block     */
                         /* where that happened (+1), [2] = 1 if a grid-wide wait gave  */
-                        /* up (results invalid), [3] reserved                          */
+                        /* up (results invalid), [3] reserved.  With NULL the library  */
+                        /* writes the same flags to a word of its own in the handle,   */
+                        /* which rqrcp_check reads                                     */
   int32_t power;        /* q in [0, 8]: steps of the power iteration of Section 6.3 on */
                         /* every sketched block, Y_i = G_i X_i (X_i^T X_i)^q; q > 0    */
                         /* needs FP64 storage (else RQRCP_ERR_UNSUPPORTED), turns the  */
@@ -122,12 +126,23 @@ void rqrcp_default_opts(rqrcp_opts_t *o);
 
 /* Create a handle bound to a HIP stream (hipStream_t passed as void*, NULL =
  * the default stream) on the current device.  Queries the device (it must be
- * gfx950) and prepares the cooperative kernels.  Errors: RQRCP_ERR_ARG
- * (h == NULL), RQRCP_ERR_UNSUPPORTED (not a gfx950 device), RQRCP_ERR_HIP. */
+ * gfx950) and prepares the cooperative kernels.  The handle owns two streams
+ * of default priority, a few events and 16 bytes of device memory (its info
+ * word), all released by rqrcp_destroy; this is the only device memory the
+ * library allocates.  Errors: RQRCP_ERR_ARG (h == NULL),
+ * RQRCP_ERR_UNSUPPORTED (not a gfx950 device), RQRCP_ERR_HIP. */
 rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream);
 rqrcp_status_t rqrcp_set_stream(rqrcp_handle_t h, void *hip_stream);
 rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h);
 const char *rqrcp_status_string(rqrcp_status_t s);
+/* Status of the most recent rqrcp_factor call on h that was given no
+ * opts.info: synchronises the handle's stream and reads the handle's own info
+ * word (layout as opts.info) into info_host (host int32[4], may be NULL).
+ * Returns RQRCP_ERR_TIMEOUT if a grid-wide wait gave up (the results of that
+ * call are invalid), else RQRCP_ERR_NONFINITE if a non-finite norm was met,
+ * else RQRCP_OK; RQRCP_ERR_ARG for a NULL handle, RQRCP_ERR_HIP if the copy
+ * fails.  Calls that were given opts.info report only there. */
+rqrcp_status_t rqrcp_check(rqrcp_handle_t h, int32_t *info_host);
 /* Message of the last failing call on h (or of the last failing call without
  * a handle when h == NULL).  Owned by the library, valid until the next call. */
 const char *rqrcp_last_error(rqrcp_handle_t h);

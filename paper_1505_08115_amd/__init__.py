@@ -10,6 +10,7 @@ Matrices are passed as torch tensors of shape (rows, cols) in column-major
 layout (``stride(0) == 1``), the layout of the C ABI.  ``colmajor(t)`` makes
 such a copy.
 """
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -20,7 +21,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librqrcp.so")
 
-RQRCP_OK, RQRCP_ERR_ARG, RQRCP_ERR_WORKSPACE, RQRCP_ERR_HIP, RQRCP_ERR_UNSUPPORTED, RQRCP_ERR_NONFINITE = range(6)
+(RQRCP_OK, RQRCP_ERR_ARG, RQRCP_ERR_WORKSPACE, RQRCP_ERR_HIP, RQRCP_ERR_UNSUPPORTED, RQRCP_ERR_NONFINITE,
+ RQRCP_ERR_TIMEOUT) = range(7)
 F64, F32 = 0, 1
 PIVOT = {"perm": 0, "ortho": 1}
 PRECISION = {"plain": 0, "mixed": 1}
@@ -29,7 +31,7 @@ TAIL = {"classical": 0, "sampled": 1}
 #: every function that include/rqrcp.h declares
 EXPORTS = [
     "rqrcp_default_opts", "rqrcp_create", "rqrcp_set_stream", "rqrcp_destroy", "rqrcp_status_string",
-    "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
+    "rqrcp_check", "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
     "rqrcp_apply_p_work_bytes", "rqrcp_apply_p", "rqrcp_lowrank_work_bytes", "rqrcp_lowrank",
     "rqrcp_lowrank_backward_work_bytes", "rqrcp_lowrank_backward", "rqrcp_sketch", "rqrcp_timing_enable",
     "rqrcp_timing_read", "rqrcp_timing_classes",
@@ -75,6 +77,7 @@ def load_library():
         "rqrcp_set_stream": (_i32, [_vp, _vp]),
         "rqrcp_destroy": (_i32, [_vp]),
         "rqrcp_status_string": (ctypes.c_char_p, [_i32]),
+        "rqrcp_check": (_i32, [_vp, _vp]),
         "rqrcp_last_error": (ctypes.c_char_p, [_vp]),
         "rqrcp_factor_sizes": (_i32, [_i32, _i64, _i64, _vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz),
                                       ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
@@ -123,6 +126,23 @@ def handle(device=None):
         h = hp
         _handles[key] = h
     return h
+
+
+def _destroy_handles():
+    """Synchronise and destroy every handle before the HIP runtime is torn
+    down at exit (their streams and events must not outlive it)."""
+    if _lib is None:
+        return
+    for key, h in list(_handles.items()):
+        try:
+            torch.cuda.synchronize(key[0])
+        except Exception:  # pragma: no cover - the runtime may already be gone
+            pass
+        _lib.rqrcp_destroy(h)
+        del _handles[key]
+
+
+atexit.register(_destroy_handles)
 
 
 def _ptr(t):
@@ -187,6 +207,19 @@ class Factorization:
     rank: int
     pivot: str
     diagonalized: bool = False    # Section 6.2: U'_i, V'_i stored in S after the T_S blocks
+    info: Optional[torch.Tensor] = None   # device int32[4], the factorization's info word
+
+    def check(self):
+        """Synchronise and read the info word: raise RqrcpError if a grid-wide
+        wait gave up (the results are invalid); otherwise return the four
+        flags ([0] = 1 if a non-finite norm was met, [1] = its block + 1)."""
+        if self.info is None:
+            return [0, 0, 0, 0]
+        torch.cuda.current_stream(self.info.device).synchronize()
+        iv = self.info.cpu().tolist()
+        if iv[2]:
+            raise RqrcpError(RQRCP_ERR_TIMEOUT, "a grid-wide wait gave up: the factorization is invalid")
+        return iv
 
 
 class Workspace:
@@ -235,12 +268,14 @@ def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain",
     T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
     S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if pivot == "ortho" else None
     jp = jpvt.to(device=dev, dtype=torch.int32).clone() if jpvt is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    if info is None:
+        info = torch.zeros(4, dtype=torch.int32, device=dev)
     ws = workspace or Workspace()
     work = ws.get(sizes[3], dev)
     factor_into(F, jp, tau, T, S, work, block=block, oversample=oversample, rank=kk, pivot=pivot,
                 precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, G=G, info=info,
                 power=power, panel_pivot=panel_pivot, diagonalize=diagonalize)
-    return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize))
+    return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize), info)
 
 
 def _plain(Fz):
@@ -294,8 +329,11 @@ def lowrank(Fz: Factorization, k=None):
 
 
 def lowrank_backward(A, Fz: Factorization, dAk, k=None):
-    """Gradient w.r.t. A of a loss of A_k, pivots held fixed (column-major in/out)."""
+    """Gradient w.r.t. A of a loss of A_k, pivots held fixed (column-major in/out).
+    Permutation form only (the library's backward reads jpvt, not S)."""
     _plain(Fz)
+    if Fz.pivot != "perm":
+        raise RqrcpError(RQRCP_ERR_UNSUPPORTED, "lowrank_backward covers the permutation form only")
     L = load_library()
     m, n = A.shape
     k = Fz.rank if k is None else int(k)
@@ -354,15 +392,12 @@ class LowRankQRCP(torch.autograd.Function):
     def forward(ctx, A, k, block=128, oversample=10, seed=0, recompute=False):
         Ac = colmajor(A.detach())
         Fz = factor(Ac, block=block, oversample=oversample, seed=seed, rank=k)
+        Fz.check()
         Ak = lowrank(Fz, k)
         ctx.k, ctx.block, ctx.recompute = int(k), int(block), bool(recompute)
         ctx.jpvt = Fz.jpvt
-        if recompute:
-            ctx.save_for_backward(Ac)
-            ctx.fz = None
-        else:
-            ctx.save_for_backward(Ac)
-            ctx.fz = Fz
+        ctx.save_for_backward(Ac)
+        ctx.fz = None if recompute else Fz
         return Ak
 
     @staticmethod
@@ -371,5 +406,6 @@ class LowRankQRCP(torch.autograd.Function):
         Fz = ctx.fz
         if Fz is None:
             Fz = factor(Ac, block=ctx.block, oversample=0, rank=ctx.k, jpvt=ctx.jpvt)
+            Fz.check()
         dA = lowrank_backward(Ac, Fz, colmajor(gAk.to(Ac.dtype)), ctx.k)
         return dA, None, None, None, None, None

@@ -30,6 +30,9 @@ struct rqrcp_ctx {
   int ncu = 0;
   hipEvent_t ev_moves = nullptr, ev_ypre = nullptr, ev_vt = nullptr, ev_upd = nullptr, ev_w = nullptr;
   hipEvent_t ev_diag = nullptr;   // the diagonalised block's work on the side stream
+  // device int32[4]: the info word of factorizations given no opts.info, so
+  // that a give-up of a grid-wide wait is never lost (read by rqrcp_check)
+  int32_t *own_info = nullptr;
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
@@ -369,6 +372,7 @@ const char *rqrcp_status_string(rqrcp_status_t s) {
     case RQRCP_ERR_HIP: return "RQRCP_ERR_HIP: HIP runtime error";
     case RQRCP_ERR_UNSUPPORTED: return "RQRCP_ERR_UNSUPPORTED: outside the supported range";
     case RQRCP_ERR_NONFINITE: return "RQRCP_ERR_NONFINITE: non-finite values";
+    case RQRCP_ERR_TIMEOUT: return "RQRCP_ERR_TIMEOUT: a grid-wide wait gave up, results invalid";
   }
   return "unknown status";
 }
@@ -399,7 +403,10 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
   hipEvent_t *evs[6] = {&c->ev_moves, &c->ev_ypre, &c->ev_vt, &c->ev_upd, &c->ev_w, &c->ev_diag};
   for (hipEvent_t *ev : evs)
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->own_info), 4 * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(c->own_info, 0, 4 * sizeof(int32_t));
   if (e != hipSuccess) {
+    if (c->own_info) (void)hipFree(c->own_info);
     for (hipEvent_t *ev : evs)
       if (*ev) (void)hipEventDestroy(*ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
@@ -407,7 +414,7 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
-    return fail_hip(nullptr, e, "side stream / events");
+    return fail_hip(nullptr, e, "side stream / events / info word");
   }
   c->ncu = prop.multiProcessorCount;
   c->device = dev;
@@ -433,7 +440,24 @@ rqrcp_status_t rqrcp_destroy(rqrcp_handle_t h) {
     if (e) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->own_info) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->own_info);
+  }
   delete h;
+  return RQRCP_OK;
+}
+
+rqrcp_status_t rqrcp_check(rqrcp_handle_t h, int32_t *info_host) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  int32_t w[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(w, h->own_info, sizeof(w), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(h, e, "reading the info word");
+  if (info_host) std::memcpy(info_host, w, sizeof(w));
+  if (w[2]) return fail(h, RQRCP_ERR_TIMEOUT, "a grid-wide wait gave up: the factorization's results are invalid");
+  if (w[0])
+    return fail(h, RQRCP_ERR_NONFINITE, "a non-finite norm was met in block " + std::to_string(w[1] - 1));
   return RQRCP_OK;
 }
 
@@ -950,8 +974,10 @@ rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64
   if (!work) return fail(h, RQRCP_ERR_WORKSPACE, "work is NULL");
   if (work_bytes < P.total) return fail(h, RQRCP_ERR_WORKSPACE, "work_bytes smaller than rqrcp_factor_sizes");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(h, RQRCP_ERR_WORKSPACE, "work must be 256-byte aligned");
-  if (dt == RQRCP_F64) return factor_impl<double>(h, P, o, static_cast<double *>(Av), lda, jpvt, tau, T, S, work);
-  return factor_impl<float>(h, P, o, static_cast<float *>(Av), lda, jpvt, tau, T, S, work);
+  rqrcp_opts_t oc = *o;
+  if (!oc.info) oc.info = h->own_info;   // flags stay readable through rqrcp_check
+  if (dt == RQRCP_F64) return factor_impl<double>(h, P, &oc, static_cast<double *>(Av), lda, jpvt, tau, T, S, work);
+  return factor_impl<float>(h, P, &oc, static_cast<float *>(Av), lda, jpvt, tau, T, S, work);
 }
 
 // ---------------------------------------------------------------------------

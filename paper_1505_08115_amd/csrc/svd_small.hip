@@ -8,7 +8,8 @@
 // rotation (a' = a - t g, b' = b + t g), so a pair needs one reduction.  At
 // convergence the columns are U' D; D is sorted in decreasing order (the
 // usual convention of the SVD), U' = columns / D, and columns whose singular
-// value is at rounding level are replaced by an orthonormal completion.
+// value is at rounding level are replaced by an orthonormal completion of the
+// others.
 #include "common.h"
 
 namespace rq {
@@ -29,6 +30,9 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
   __shared__ double nrm[kSvdMaxB];   // squared column norms within a sweep
   __shared__ int order[kSvdMaxB];
   __shared__ int rotated;
+  __shared__ int accepted[kSvdMaxB];
+  __shared__ double resid[kSvdMaxB], coef[kSvdMaxB];
+  __shared__ int pick;
   const int t = threadIdx.x;
   const int n = nb;
   const int ne = (n + 1) & ~1;   // an odd count gets a zero column that never rotates
@@ -126,35 +130,63 @@ __global__ __launch_bounds__(kSvdThreads) void svd_jacobi_kernel(double *__restr
     if (sc > thr && sc > 0.0) a[c][r] = a[c][r] / sc;
   }
   __syncthreads();
-  if (t == 0) {
-    // orthonormal completion of the columns at rounding level, in sorted
-    // order, from the unit vectors (two Gram-Schmidt passes each)
-    int e = 0;
-    for (int j = 0; j < n; ++j) {
-      const int c = order[j];
-      if (sig[c] > thr && sig[c] > 0.0) continue;
-      for (; e < n; ++e) {
-        for (int r = 0; r < n; ++r) a[c][r] = r == e ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int jj = 0; jj < n; ++jj) {
-            const int o = order[jj];
-            if (o == c || (!(sig[o] > thr && sig[o] > 0.0) && jj > j)) continue;
-            double d = 0.0;
-            for (int r = 0; r < n; ++r) d += a[o][r] * a[c][r];
-            for (int r = 0; r < n; ++r) a[c][r] -= d * a[o][r];
-          }
-        double nn = 0.0;
-        for (int r = 0; r < n; ++r) nn += a[c][r] * a[c][r];
-        nn = sqrt(nn);
-        if (nn > 0.5) {
-          for (int r = 0; r < n; ++r) a[c][r] /= nn;
-          ++e;
-          break;
-        }
-      }
-    }
-  }
+  // Orthonormal completion of the columns at rounding level, in sorted
+  // order.  With the accepted columns orthonormal, unit vector e keeps the
+  // squared residual 1 - sum_o u_o(e)^2 after projection; these residuals sum
+  // to the number d of missing directions, so the largest is at least d/n
+  // and the choice below never fails, whatever subspace the accepted columns
+  // span.  The chosen unit vector is orthogonalised by two passes of
+  // classical Gram-Schmidt and normalised.
+  if (t < n) accepted[t] = (sig[t] > thr && sig[t] > 0.0) ? 1 : 0;
   __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int c = order[j];
+    if (accepted[c]) continue;   // uniform: every thread reads the same LDS word
+    if (t < n) {
+      double s2 = 0.0;
+      for (int o = 0; o < n; ++o)
+        if (accepted[o]) s2 += a[o][t] * a[o][t];
+      resid[t] = 1.0 - s2;
+    }
+    __syncthreads();
+    if (t == 0) {
+      int best = 0;
+      for (int e = 1; e < n; ++e)
+        if (resid[e] > resid[best]) best = e;
+      pick = best;
+    }
+    __syncthreads();
+    const int e = pick;
+    if (t < n) a[c][t] = t == e ? 1.0 : 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (t < n) {
+        double d = 0.0;
+        if (accepted[t])
+          for (int r = 0; r < n; ++r) d += a[t][r] * a[c][r];
+        coef[t] = d;
+      }
+      __syncthreads();
+      double x = 0.0;
+      if (t < n) {
+        x = a[c][t];
+        for (int o = 0; o < n; ++o)
+          if (accepted[o]) x -= coef[o] * a[o][t];
+      }
+      __syncthreads();
+      if (t < n) a[c][t] = x;
+      __syncthreads();
+    }
+    if (t == 0) {
+      double nn = 0.0;
+      for (int r = 0; r < n; ++r) nn += a[c][r] * a[c][r];
+      resid[0] = sqrt(nn);
+      accepted[c] = 1;
+    }
+    __syncthreads();
+    if (t < n) a[c][t] /= resid[0];
+    __syncthreads();
+  }
   for (int i = t; i < n * n; i += kSvdThreads) {
     const int j = i / n, r = i % n;
     const int c = order[j];

@@ -53,7 +53,7 @@ def test_default_options_and_status_strings(lib):
     lib.rqrcp_default_opts(ctypes.byref(o))
     assert (o.block, o.oversample, o.rank, o.pivot, o.precision, o.tail, o.fixed_pivots) == (128, 10, 0, 0, 0, 0, 0)
     assert o.seed == 0 and not o.G and not o.info and o.power == 0 and o.panel_pivot == 0 and o.diagonalize == 0
-    for st in range(6):
+    for st in range(7):
         assert lib.rqrcp_status_string(st)
 
 

@@ -1,0 +1,246 @@
+"""GPU parity at the full sizes of the configured workloads (through the C ABI).
+
+These cases run the library on the GPU at the sizes the benchmark and the
+configuration table name, and the oracle on the CPU on as many leading blocks
+as it finishes in seconds:
+
+  * H1 (8192^2 FP64, b = 256, p = 10, permutation form): pivots bit-exact on
+    the oracle's separated prefix over the first four blocks, R(0:pre, :) P^T
+    within 1e-10, invariants of the whole factorization, sigma-tracking.
+  * C3 (8192^2 FP64, b = 256, p = 10, orthonormal form): residual, Q^T Q and
+    P^T P of the whole factorization, R's first two blocks of rows against the
+    oracle within max(1e-10, u kappa).
+  * H2 (8192^2) and C4 (16384 x 8192), FP32 storage with the BF16 sketch,
+    against the FP64 oracle run on the FP32-rounded input: residual <= 1e-5,
+    orthogonality, sigma-tracking; pivot agreement is reported (the BF16
+    sketch moves close decisions, so it does not bind).
+  * C5 (4096^2, k = 256, b = 128): the backward of the truncation against the
+    oracle's gradient, against central differences on 32 directions (FP64,
+    h = 1e-6, difference taken first), through LowRankQRCP with the WY blocks
+    kept and with recompute; the FP32 backward against the oracle.
+
+Singular values: the inputs are U diag(s) V^T with prescribed s, so s are the
+exact singular values of the FP64 input (to |fl(A) - A|_2, Weyl) and serve as
+sigma in the tracking ratio gamma = max_i max(|R_ii|/s_i, s_i/|R_ii|).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1505_08115_amd as R
+import workloads as W
+from oracle import rqrcp as O
+from tests.parity import first_mismatch, progress, r_times_pt, separated_prefix, sign_rows
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+U64 = 2.0 ** -53
+
+
+def _residual_orth(A, Fz):
+    """|A P - Q R|_F / |A|_F and |Q^T Q - I|_F in FP64, with Q rebuilt from the
+    stored reflectors by torch (LAPACK orgqr semantics), independently of this
+    library.  A is the FP64 matrix the factorization saw (FP32-rounded for FP32
+    storage)."""
+    F = Fz.F.double()
+    k = Fz.rank
+    Q = torch.linalg.householder_product(F[:, :k].contiguous(), Fz.tau[:k].contiguous())
+    if Fz.pivot == "perm":
+        AP = A[:, Fz.jpvt.long()]
+    else:
+        AP = R.apply_p(Fz, R.colmajor(A.clone()), trans=False)
+    res = float(torch.linalg.norm(AP - Q @ torch.triu(F[:k, :])) / torch.linalg.norm(A))
+    del AP
+    orth = float(torch.linalg.norm(Q.T @ Q - torch.eye(k, device=A.device, dtype=torch.float64)))
+    return res, orth
+
+
+def _gamma(diag, s, rank):
+    d, s = np.abs(diag[:rank]), s[:rank]
+    return float(np.max(np.maximum(d / s, s / d)))
+
+
+def test_H1_pivots_over_four_blocks_and_full_invariants():
+    """H1 at its full size: the oracle runs the first four blocks (rank 1024)
+    with its own sketches; the GPU draws the same sketches on the device."""
+    w = W.WORKLOADS["H1"]
+    progress("H1: generating the input on the GPU")
+    A_dev = W.workload_matrix(w, device=DEV)
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed)
+    progress(f"H1: GPU done, info {Fz.check()}")
+    assert Fz.check() == [0, 0, 0, 0]
+    res, orth = _residual_orth(A_dev, Fz)
+    progress(f"H1: residual {res:.2e}, orthogonality {orth:.2e}")
+    assert res <= 1e-12 and orth <= 1e-11
+    A = A_dev.cpu().numpy()
+    jg = Fz.jpvt.cpu().numpy()
+    assert np.array_equal(np.sort(jg), np.arange(w.n))
+    d = np.abs(np.diag(Fz.F.cpu().numpy()))
+    gamma = _gamma(d, w.sigma(), w.n)
+    progress(f"H1: gamma {gamma:.3e} (bound 10 sqrt(n) = {10 * np.sqrt(w.n):.0f}); oracle on 4 blocks")
+    assert gamma <= 10 * np.sqrt(w.n)
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed, rank=4 * w.b)
+    pre = separated_prefix(ref)
+    bad = first_mismatch(jg[:pre], ref["jpvt"][:pre])
+    progress(f"H1: separated prefix {pre} of {4 * w.b}, first mismatch {bad}")
+    assert bad < 0, f"pivots differ at position {bad}"
+    assert pre == 4 * w.b, f"H1's first four blocks should be separated, prefix {pre}"
+    Fg = Fz.F.cpu().numpy()
+    dR = np.linalg.norm(r_times_pt(Fg, jg, pre) - r_times_pt(ref["F"], ref["jpvt"], pre)) / \
+        np.linalg.norm(r_times_pt(ref["F"], ref["jpvt"], pre))
+    progress(f"H1: R(0:{pre}, :) P^T differs by {dR:.2e}")
+    assert dR <= 1e-10
+
+
+def test_C3_ortho_full_size():
+    """C3: orthonormal pivoting at 8192^2, b = 256 (Section 4.2)."""
+    w = W.WORKLOADS["C3"]
+    progress("C3: generating the input on the GPU")
+    A_dev = W.workload_matrix(w, device=DEV)
+    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed, pivot="ortho")
+    assert Fz.check() == [0, 0, 0, 0]
+    res, orth = _residual_orth(A_dev, Fz)
+    P = R.apply_p(Fz, R.colmajor(torch.eye(w.n, dtype=torch.float64, device=DEV)), trans=False)
+    porth = float(torch.linalg.norm(P.T @ P - torch.eye(w.n, dtype=torch.float64, device=DEV)))
+    del P
+    progress(f"C3: residual {res:.2e}, |Q^TQ - I| {orth:.2e}, |P^TP - I| {porth:.2e}")
+    assert res <= 1e-12 and orth <= 1e-11 and porth <= 1e-11
+    A = A_dev.cpu().numpy()
+    progress("C3: oracle on 2 blocks")
+    ref = O.rqrcp(A, w.b, w.p, seed=w.seed, pivot="ortho", rank=2 * w.b, trace=True)
+    rows = 2 * w.b
+    # S_i is the Q factor of the QR of Y_i(1:b_i, :)^T, fixed by rounding to
+    # about u cond_2 of that block; Y_i carries relative differences of about
+    # u |A| / |X_i| between the two sides
+    kap = max(np.linalg.cond(Y[:bi]) * ref["xnorm"][0] / xn
+              for (_, bi), Y, xn in zip(ref["blocks"], ref["Y"], ref["xnorm"]))
+    tol = max(1e-10, U64 * kap)
+    Rg = sign_rows(np.triu(Fz.F.cpu().numpy()[:rows]))
+    Ro = sign_rows(np.triu(ref["F"][:rows]))
+    dR = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    progress(f"C3: R(0:{rows}, :) differs by {dR:.2e} (tolerance {tol:.1e})")
+    assert dR <= tol
+    s = w.sigma()
+    d = np.abs(np.diag(Fz.F.cpu().numpy()))
+    rank = int(np.sum(s > s[0] * 1e-13))
+    gamma = _gamma(d, s, rank)
+    progress(f"C3: gamma {gamma:.3e}")
+    assert gamma <= 10 * np.sqrt(w.n)
+
+
+MIXED = [("H2", 4), ("C4", 2)]
+
+
+@pytest.mark.parametrize("name,oracle_blocks", MIXED)
+def test_mixed_precision_against_the_fp64_oracle(name, oracle_blocks):
+    """FP32 storage, BF16 sketch (FP32 accumulation), FP32 matrix-core
+    update, FP64 panel, T and pivoted QR of the sketch; every error is taken
+    against the FP32-rounded input, which the FP64 oracle also factors."""
+    w = W.WORKLOADS[name]
+    progress(f"{name}: generating the input on the GPU")
+    A64 = W.workload_matrix(w, device=DEV)
+    A32 = R.colmajor(A64.float())
+    Ar = A32.double()                       # the matrix both sides factor
+    rounding = float(torch.linalg.norm(Ar - A64) / torch.linalg.norm(A64))
+    del A64
+    Fz = R.factor(A32, block=w.b, oversample=w.p, seed=w.seed, precision="mixed")
+    assert Fz.check() == [0, 0, 0, 0]
+    res, orth = _residual_orth(Ar, Fz)
+    progress(f"{name}: |fl32(A) - A|/|A| {rounding:.2e}, residual {res:.2e}, orthogonality {orth:.2e}")
+    assert res <= 1e-5, f"residual {res:.3e}"
+    assert orth <= 1e-4, f"orthogonality {orth:.3e}"
+    s = w.sigma()
+    d = np.abs(np.diag(Fz.F.double().cpu().numpy()))
+    gamma = _gamma(d, s, w.n)
+    progress(f"{name}: gamma {gamma:.3e}")
+    assert gamma <= 10 * np.sqrt(w.n)
+    k = oracle_blocks * w.b
+    progress(f"{name}: FP64 oracle on {oracle_blocks} blocks")
+    ref = O.rqrcp(Ar.cpu().numpy(), w.b, w.p, seed=w.seed, rank=k)
+    do = np.abs(np.diag(ref["F"]))[:k]
+    track = float(np.max(np.abs(d[:k] / s[:k] - do / s[:k])))
+    gamma_or = _gamma(do, s, k)
+    agree = first_mismatch(Fz.jpvt.cpu().numpy()[:k], ref["jpvt"][:k])
+    same = len(np.intersect1d(Fz.jpvt.cpu().numpy()[:k], ref["jpvt"][:k]))
+    progress(f"{name}: sigma-tracking max | |R_ii|/s_i - |R_ii^or|/s_i | over i < {k}: {track:.3e}; "
+             f"oracle gamma {gamma_or:.3e}; pivots agree up to {agree if agree >= 0 else k}, "
+             f"{same} of the first {k} pivot columns shared")
+    # both factorizations reveal the rank to the same degree: their diagonals
+    # follow s within the same factor, whatever the individual pivots
+    assert track <= 1.0
+    assert gamma_or <= 10 * np.sqrt(w.n)
+
+
+def _c5_inputs(dtype=torch.float64):
+    w = W.WORKLOADS["C5"]
+    A = R.colmajor(W.workload_matrix(w, device=DEV).to(dtype))
+    B = W.gaussian_matrix(w.m, w.n, seed=w.seed).to(DEV)
+    return w, A, B
+
+
+def test_C5_backward_matches_oracle_gradient():
+    w, A, B = _c5_inputs()
+    k = w.rank
+    Fz = R.factor(A, block=w.b, oversample=w.p, seed=w.seed, rank=k)
+    assert Fz.check() == [0, 0, 0, 0]
+    Gbar = R.colmajor(2 * (R.lowrank(Fz, k) - B))
+    dA = R.lowrank_backward(A, Fz, Gbar, k).cpu().numpy()
+    ref = O.lowrank_grad(A.cpu().numpy(), Fz.jpvt.cpu().numpy(), k, Gbar.cpu().numpy())
+    err = np.linalg.norm(dA - ref) / np.linalg.norm(ref)
+    progress(f"C5 FP64 backward vs oracle gradient: relative Frobenius {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_C5_fp32_backward_against_the_oracle():
+    w, A32, B = _c5_inputs(torch.float32)
+    k = w.rank
+    Fz = R.factor(A32, block=w.b, oversample=w.p, seed=w.seed, rank=k)
+    assert Fz.check() == [0, 0, 0, 0]
+    Gbar = R.colmajor((2 * (R.lowrank(Fz, k).double() - B)).float())
+    dA = R.lowrank_backward(A32, Fz, Gbar, k).double().cpu().numpy()
+    ref = O.lowrank_grad(A32.double().cpu().numpy(), Fz.jpvt.cpu().numpy(), k, Gbar.double().cpu().numpy())
+    err = np.linalg.norm(dA - ref) / np.linalg.norm(ref)
+    progress(f"C5 FP32 backward vs oracle gradient: relative Frobenius {err:.2e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+def test_C5_backward_central_differences(recompute):
+    """L(A) = |A_k - B|_F^2 through LowRankQRCP (autograd), pivots fixed by the
+    forward.  For 32 unit directions E (i.i.d. N(0,1) scaled to |E|_F = 1):
+    FD = <f(A+hE) - f(A-hE), f(A+hE) + f(A-hE) - 2B> / (2h) with h = 1e-6,
+    f evaluated by a fixed-pivot factorization, against <dL/dA, E>; per
+    direction |FD - <g, E>| <= 1e-6 max(|<g, E>|, |g|_F |E|_F / sqrt(m n))."""
+    w, A, B = _c5_inputs()
+    k, h = w.rank, 1e-6
+    At = A.clone().requires_grad_(True)
+    Ak = R.LowRankQRCP.apply(At, k, w.b, w.p, w.seed, recompute)
+    loss = torch.sum((Ak - B) ** 2)
+    loss.backward()
+    g = At.grad.detach()
+    jp = R.factor(A, block=w.b, oversample=w.p, seed=w.seed, rank=k).jpvt
+    # the oracle's gradient at the same pivots, as a second reference
+    ref = O.lowrank_grad(A.cpu().numpy(), jp.cpu().numpy(), k, (2 * (Ak.detach() - B)).cpu().numpy())
+    gerr = float(np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref))
+    progress(f"C5 autograd (recompute={recompute}) vs oracle gradient: {gerr:.2e}")
+    assert gerr <= 1e-10
+
+    def f(X):
+        Fx = R.factor(R.colmajor(X), block=w.b, oversample=0, rank=k, jpvt=jp)
+        Fx.check()
+        return R.lowrank(Fx, k)
+
+    gen = torch.Generator(device="cpu").manual_seed(w.seed * 1000003 + 5)
+    gn = float(torch.linalg.norm(g))
+    worst = 0.0
+    for d in range(32):
+        E = torch.randn(w.m, w.n, generator=gen, dtype=torch.float64).to(DEV)
+        E /= torch.linalg.norm(E)
+        fp, fm = f(A + h * E), f(A - h * E)
+        fd = float(torch.sum((fp - fm) * (fp + fm - 2 * B))) / (2 * h)
+        an = float(torch.sum(g * E))
+        scale = max(abs(an), gn / np.sqrt(w.m * w.n))
+        rel = abs(fd - an) / scale
+        worst = max(worst, rel)
+        assert rel <= 1e-6, f"direction {d}: FD {fd:.12e} vs analytic {an:.12e} ({rel:.2e})"
+    progress(f"C5 central differences (recompute={recompute}): worst scaled error {worst:.2e} over 32 directions")

@@ -250,7 +250,9 @@ def test_C2_parity_and_exact_rank(name):
     ref = O.rqrcp(A, w.b, w.p, seed=w.seed, rank=1024 if name == "C2r" else 0)
     progress(f"{name}: oracle done; comparing")
     pre = _compare(A, Fz, ref)
-    assert pre >= 512, f"separated prefix only {pre}"
+    # measured on MI355X: 2344 (C2, where the singular values reach 1e-12 and
+    # later decisions fall within rounding) and 1000 (C2r, its exact rank)
+    assert pre >= (1000 if name == "C2r" else 2300), f"separated prefix only {pre}"
     progress(f"{name}: separated prefix {pre}; invariants")
     _invariants(A, Fz)
     progress(f"{name}: invariants ok")
@@ -278,29 +280,6 @@ def test_C3_subcase_ortho_tracks_singular_values():
     assert np.max(np.abs(dg[:rank] / sv[:rank] - do[:rank] / sv[:rank])) <= 1e-6
     gamma = np.max(np.maximum(dg[:rank] / sv[:rank], sv[:rank] / dg[:rank]))
     assert gamma <= 10 * np.sqrt(w.n), f"gamma {gamma:.3e}"
-
-
-def test_H1_full_size_properties_and_first_block_pivots():
-    """n = 8192 in the benchmark's configuration: invariants at full size,
-    and the first block's pivots against the oracle's sketch and QRCP."""
-    w = W.WORKLOADS["H1"]
-    progress("H1: generating the input on the GPU")
-    A_dev = W.workload_matrix(w, device=DEV)
-    info = torch.zeros(4, dtype=torch.int32, device=DEV)
-    progress("H1: GPU factorization")
-    Fz = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed, info=info)
-    torch.cuda.synchronize()
-    progress(f"H1: GPU done, info {info.tolist()}")
-    assert info.cpu().tolist() == [0, 0, 0, 0]
-    m, n = A_dev.shape
-    _invariants(A_dev.cpu().numpy(), Fz, tol_res=1e-12, tol_orth=1e-11)
-    A = A_dev.cpu().numpy()
-    G0 = philox.sketch_block(w.seed, 0, w.b + w.p, 0, m)
-    Y = G0 @ A
-    piv, jp, _, mg = O.qrcp(Y, steps=w.b, record_margins=True)
-    sep = int(np.argmax(~(mg > 1e-10))) if np.any(~(mg > 1e-10)) else w.b
-    assert sep >= 200
-    assert first_mismatch(Fz.jpvt.cpu().numpy()[:sep], jp[:sep]) < 0
 
 
 def test_apply_q_apply_p_lowrank_match_oracle():
@@ -590,3 +569,30 @@ def test_panel_pivoting_matches_oracle(m, n, b, p, rank, tail, q, shared):
     for r0 in range(0, k, b):
         blk = d[r0:min(k, r0 + b)]
         assert np.all(blk[:-1] >= blk[1:] * (1 - 1e-12)), f"block at {r0}"
+
+
+def test_check_reads_the_handle_info_word():
+    """With no opts.info the library keeps the flags in the handle's own word;
+    rqrcp_check (C ABI) synchronises and reports them."""
+    import ctypes
+    L = R.load_library()
+    m, n, b = 64, 64, 16
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 2.0), seed=1).numpy()
+    sizes = R.factor_sizes(m, n, block=b, oversample=4)
+    jp = torch.empty(n, dtype=torch.int32, device=DEV)
+    tau = torch.empty(sizes[0], dtype=torch.float64, device=DEV)
+    T = torch.empty(sizes[1], dtype=torch.float64, device=DEV)
+    work = torch.empty(sizes[3], dtype=torch.uint8, device=DEV)
+    h = R.handle()
+    iv = (ctypes.c_int32 * 4)()
+    for bad in (True, False):
+        X = A.copy()
+        if bad:
+            X[5, 7] = np.inf
+        F = R.colmajor(torch.tensor(X, device=DEV))
+        R.factor_into(F, jp, tau, T, None, work, block=b, oversample=4, seed=1)
+        st = L.rqrcp_check(h, iv)
+        if bad:
+            assert st == R.RQRCP_ERR_NONFINITE and iv[0] == 1 and iv[1] >= 1 and iv[2] == 0
+        else:
+            assert st == R.RQRCP_OK and list(iv) == [0, 0, 0, 0]

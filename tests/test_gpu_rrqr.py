@@ -136,3 +136,29 @@ def test_diagonalised_blocks_of_rank_deficient_inputs(rank_a):
     assert np.linalg.norm(Q.T @ A @ P - Rg) / nA <= 1e-13
     assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 1e-12
     assert np.linalg.norm(P.T @ P - np.eye(n)) <= 1e-12
+
+
+def test_orthonormal_completion_with_noise_across_the_threshold():
+    """Rank 20 plus trailing singular values spread from 1e-11 to 1e-18: the
+    triangles past the rank hold rounding-level entries on both sides of the
+    Jacobi kernel's acceptance threshold (b eps times the triangle's largest
+    singular value), so some columns of U' come from the rotations and the
+    rest from the orthonormal completion; U' must stay orthogonal."""
+    m, n, b = 120, 96, 16
+    s = np.concatenate([np.ones(20), np.geomspace(1e-11, 1e-18, n - 20)])
+    A = W.make_matrix(m, n, s, seed=17).numpy()
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=8, seed=5, pivot="ortho", power=1,
+                  diagonalize=True)
+    assert Fz.check() == [0, 0, 0, 0]
+    res = _as_result(Fz, m, n, b)
+    worst = 0.0
+    for u, v in res["D"]:
+        bi = u.shape[0]
+        worst = max(worst, np.linalg.norm(u.T @ u - np.eye(bi)), np.linalg.norm(v.T @ v - np.eye(bi)))
+    progress(f"completion across the threshold: worst |U'^T U' - I|, |V'^T V' - I| = {worst:.2e}")
+    assert worst <= 1e-12
+    Q, P = O.form_q(res, m), O.form_p(res)
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(Q.T @ A @ P - np.triu(res["F"])) / nA <= 1e-13
+    assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 1e-12
+    assert np.linalg.norm(P.T @ P - np.eye(n)) <= 1e-12
