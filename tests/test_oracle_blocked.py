@@ -192,3 +192,29 @@ def test_rejects_wide_matrices_and_bad_rank():
         O.rqrcp(np.zeros((3, 5)), 2, 1, seed=0)
     with pytest.raises(ValueError):
         O.rqrcp(np.zeros((5, 5)), 2, 1, seed=0, rank=9)
+
+
+@pytest.mark.parametrize("m,n,b,p", [(200, 160, 32, 8), (150, 150, 40, 0), (300, 250, 64, 20)])
+def test_ortho_S_equals_lapack_qr_of_the_sketch_transpose(m, n, b, p):
+    """Section 4.2 (eq. Ycols and its Remark): S_i = H_1 ... H_{b_i} of the
+    unpivoted Householder QR of Y_i^T.  LAPACK's dgeqrf of Y_i^T (all b+p
+    columns; the first b_i reflectors depend only on the first b_i columns)
+    must give the same reflectors and scalars (dlarfg takes beta =
+    -sign(alpha) |x|, the paper's sign), and its explicit Q the same first
+    b_i columns as I - V_S T_S V_S^T.  A transposed sketch, a pivoted QR or a
+    wrong block of rows would fail here."""
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 3.0), seed=m + b).numpy()
+    ref = O.rqrcp(A, b, p, seed=4, pivot="ortho", trace=True)
+    for (r0, bi), Y, (VS, ts, TS) in zip(ref["blocks"], ref["Y"], ref["S"]):
+        ni = n - r0
+        qr, tau, _, info = sla.lapack.dgeqrf(Y.T.copy())
+        assert info == 0
+        VL = np.tril(qr[:, :bi], -1)
+        VL[np.arange(bi), np.arange(bi)] = 1.0
+        scale = np.linalg.cond(Y[:bi]) * 1e-14
+        np.testing.assert_allclose(ts, tau[:bi], rtol=0, atol=scale)
+        np.testing.assert_allclose(VS, VL, rtol=0, atol=scale * max(1.0, np.abs(VL).max()))
+        QL, _, info = sla.lapack.dorgqr(qr[:, :bi].copy(), tau[:bi].copy())
+        assert info == 0
+        S = np.eye(ni) - VS @ TS @ VS.T
+        np.testing.assert_allclose(S[:, :bi], QL, rtol=0, atol=scale)

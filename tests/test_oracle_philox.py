@@ -52,3 +52,31 @@ def test_sketch_entries_depend_only_on_their_counter():
     np.testing.assert_array_equal(G[:5, 20:30], Gsub)
     Gother = philox.sketch_block(seed=2, block=2, nsample=12, row0=100, nrows=50)
     assert np.all(G != Gother)
+
+
+def _box_muller_cases():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "box_muller_examples.txt")
+    out = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        seed, tag, ctr, w0, w1, z = [f.strip() for f in line.split("|")]
+        out.append((int(seed), int(tag), tuple(int(c) for c in ctr.split(",")), int(w0), int(w1), float(z)))
+    return out
+
+
+@pytest.mark.parametrize("seed,tag,ctr,w0,w1,z", _box_muller_cases())
+def test_sketch_entries_match_known_answers(seed, tag, ctr, w0, w1, z):
+    # words from numpy's Philox, normals from a 50-digit decimal evaluation of
+    # Box-Muller (tests/golden/make_box_muller.py): pins the uniform map and
+    # the transform (a wrong shift, constant, or cos/sin swap fails here)
+    got_w = philox.philox4x64_10(*[np.uint64(c) for c in ctr], np.uint64(seed), np.uint64(tag))
+    assert [int(got_w[0]), int(got_w[1])] == [w0, w1]
+    got = float(philox.normal_from_counter(*[np.uint64(c) for c in ctr], seed, tag))
+    assert abs(got - z) <= 4 * np.spacing(abs(z)), (got, z)
+    if tag == philox.TAG_SKETCH and ctr[3] == 0:
+        # the same entry of the block sketch: counter (g, r, i, 0)
+        g, r, i = ctr[0], ctr[1], ctr[2]
+        G = philox.sketch_block(seed, i, r + 1, g, 1)
+        assert abs(G[r, 0] - z) <= 4 * np.spacing(abs(z))
