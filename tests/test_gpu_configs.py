@@ -8,8 +8,10 @@ as it finishes in seconds:
     the oracle's separated prefix over the first four blocks, R(0:pre, :) P^T
     within 1e-10, invariants of the whole factorization, sigma-tracking.
   * C3 (8192^2 FP64, b = 256, p = 10, orthonormal form): residual, Q^T Q and
-    P^T P of the whole factorization, R's first two blocks of rows against the
-    oracle within max(1e-10, u kappa).
+    P^T P of the whole factorization; R(0:2b, 0:2b) and the row norms of
+    R(0:2b, 2b:n) against the oracle's first two blocks (later rotations only
+    turn those rows' trailing columns), and every entry of R(0:2b, :) of a
+    rank-2b GPU run, within max(1e-10, u kappa).
   * H2 (8192^2) and C4 (16384 x 8192), FP32 storage with the BF16 sketch,
     against the FP64 oracle run on the FP32-rounded input: residual <= 1e-5,
     orthogonality, sigma-tracking; pivot agreement is reported (the BF16
@@ -105,6 +107,12 @@ def test_C3_ortho_full_size():
     del P
     progress(f"C3: residual {res:.2e}, |Q^TQ - I| {orth:.2e}, |P^TP - I| {porth:.2e}")
     assert res <= 1e-12 and orth <= 1e-11 and porth <= 1e-11
+    s = w.sigma()
+    d = np.abs(np.diag(Fz.F.cpu().numpy()))
+    rank = int(np.sum(s > s[0] * 1e-13))
+    gamma = _gamma(d, s, rank)
+    progress(f"C3: gamma {gamma:.3e}")
+    assert gamma <= 10 * np.sqrt(w.n)
     A = A_dev.cpu().numpy()
     progress("C3: oracle on 2 blocks")
     ref = O.rqrcp(A, w.b, w.p, seed=w.seed, pivot="ortho", rank=2 * w.b, trace=True)
@@ -115,17 +123,27 @@ def test_C3_ortho_full_size():
     kap = max(np.linalg.cond(Y[:bi]) * ref["xnorm"][0] / xn
               for (_, bi), Y, xn in zip(ref["blocks"], ref["Y"], ref["xnorm"]))
     tol = max(1e-10, U64 * kap)
-    Rg = sign_rows(np.triu(Fz.F.cpu().numpy()[:rows]))
     Ro = sign_rows(np.triu(ref["F"][:rows]))
-    dR = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
-    progress(f"C3: R(0:{rows}, :) differs by {dR:.2e} (tolerance {tol:.1e})")
+    # the full factorization: later blocks rotate columns rows:n of every row
+    # (S_i acts on all m rows, Section 4.2), so only R(0:rows, 0:rows) and the
+    # row norms of R(0:rows, rows:n) are fixed by the first two blocks
+    Rg = sign_rows(np.triu(Fz.F.cpu().numpy()[:rows]))
+    dL = np.linalg.norm(Rg[:, :rows] - Ro[:, :rows]) / np.linalg.norm(Ro[:, :rows])
+    nr_g, nr_o = np.linalg.norm(Rg[:, rows:], axis=1), np.linalg.norm(Ro[:, rows:], axis=1)
+    dN = np.max(np.abs(nr_g - nr_o)) / np.max(nr_o)
+    progress(f"C3: R(0:{rows}, 0:{rows}) differs by {dL:.2e}, row norms of R(0:{rows}, {rows}:) by {dN:.2e} "
+             f"(tolerance {tol:.1e})")
+    assert dL <= tol and dN <= tol
+    del Fz
+    # the same two blocks on the GPU: every entry of R(0:rows, :)
+    A_dev = W.workload_matrix(w, device=DEV)
+    F2 = R.factor(A_dev, block=w.b, oversample=w.p, seed=w.seed, pivot="ortho", rank=rows)
+    assert F2.check() == [0, 0, 0, 0]
+    Rg2 = sign_rows(np.triu(F2.F.cpu().numpy()[:rows]))
+    dR = np.linalg.norm(Rg2 - Ro) / np.linalg.norm(Ro)
+    progress(f"C3 at rank {rows}: R(0:{rows}, :) differs by {dR:.2e} (tolerance {tol:.1e})")
     assert dR <= tol
-    s = w.sigma()
-    d = np.abs(np.diag(Fz.F.cpu().numpy()))
-    rank = int(np.sum(s > s[0] * 1e-13))
-    gamma = _gamma(d, s, rank)
-    progress(f"C3: gamma {gamma:.3e}")
-    assert gamma <= 10 * np.sqrt(w.n)
+    del F2, A_dev
 
 
 MIXED = [("H2", 4), ("C4", 2)]
@@ -156,7 +174,8 @@ def test_mixed_precision_against_the_fp64_oracle(name, oracle_blocks):
     assert gamma <= 10 * np.sqrt(w.n)
     k = oracle_blocks * w.b
     progress(f"{name}: FP64 oracle on {oracle_blocks} blocks")
-    ref = O.rqrcp(Ar.cpu().numpy(), w.b, w.p, seed=w.seed, rank=k)
+    # row-major copy: the oracle slices columns (the column-major view is many times slower)
+    ref = O.rqrcp(np.ascontiguousarray(Ar.cpu().numpy()), w.b, w.p, seed=w.seed, rank=k)
     do = np.abs(np.diag(ref["F"]))[:k]
     track = float(np.max(np.abs(d[:k] / s[:k] - do / s[:k])))
     gamma_or = _gamma(do, s, k)
