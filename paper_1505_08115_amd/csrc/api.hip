@@ -92,6 +92,18 @@ size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
   return sp > 1 ? (size_t)sp * M * N : 0;
 }
 
+// The same for an FP32 product (the all-rows engine takes more rows in FP32).
+size_t gemm_part_floats(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  int sp = 1;
+  for (int tb = 0; tb < 2; ++tb) {
+    GemmF32 g{};
+    g.M = M; g.N = N; g.K = K; g.tb = tb != 0;
+    sp = std::max(sp, gemm_splits<float>(g));
+  }
+  return sp > 1 ? (size_t)sp * M * N : 0;
+}
+
 struct FactorPlan {
   int64_t m = 0, n = 0, b = 0, p = 0, k = 0, ks = 0, nblocks = 0;
   bool ortho = false, fixed = false, classical_tail = false, f32 = false, mixed = false;
@@ -100,6 +112,7 @@ struct FactorPlan {
   bool diag = false;          // diagonalised blocks (Section 6.2)
   // FP32-storage buffers
   size_t Pw = 0, V32 = 0, VT32 = 0, Vt32 = 0, W32 = 0, gpart32 = 0, Gb = 0, spart = 0, G32 = 0, Y32 = 0, VS32 = 0, TS32 = 0;
+  size_t gpart32_aux = 0;   // split-K room of the FP32 trailing update on the auxiliary stream
   int nslots = 0;
   // byte offsets into the workspace
   size_t G = 0, Y = 0, YT = 0, Vb = 0, VT = 0, Vt = 0, Wb = 0, gpart = 0, Sg = 0, ppart = 0, pred = 0, qrec = 0, qcand = 0,
@@ -232,8 +245,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (!P.f32) gpart32 = 0;
   // the next block's sketch product and this block's trailing update may run
   // on the auxiliary stream (own split-K room), the correction G V on the main
-  P.pipe = !P.f32 && !P.ortho && !P.fixed && P.power == 0;
-  size_t gpaux = 0;
+  P.pipe = (!P.f32 || P.mixed) && !P.ortho && !P.fixed && P.power == 0;
+  size_t gpaux = 0, gpaux32 = 0;
   if (P.pipe)
     for (int64_t i = 0; i + 1 < P.nblocks; ++i) {
       const int64_t r0 = i * P.b, bi = std::min(P.b, P.k - r0), mi = m - r0, ni = n - r0;
@@ -244,6 +257,10 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
       gpart = std::max(gpart, gemm_part_doubles(P.ks, bi, mi - bi));
       gpart = std::max(gpart, gemm_part_doubles(P.ks, ni - bi, bi));
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));     // T^T W
+      if (P.f32) {
+        gpart = std::max(gpart, gemm_part_doubles(P.ks, bi, bi));       // (G V) T^T
+        gpaux32 = std::max(gpaux32, gemm_part_floats(mi, ni - bi, bi));  // the FP32 update beside the QR
+      }
     }
   P.Y_doubles = Yd;
   // cooperative launches per block: pivoted QR of the sketch (or the
@@ -294,6 +311,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     P.Y32 = w.take(sampled && !P.mixed ? (size_t)P.ks * n * 4 : 0);
     P.VS32 = w.take(P.ortho ? (size_t)n * P.b * 4 : 0);
     P.TS32 = w.take(P.ortho ? (size_t)P.b * P.b * 4 : 0);
+    P.gpart32_aux = w.take(gpaux32 * 4);
   }
   P.total = w.off + 256;
   *out = P;
@@ -560,6 +578,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   float *V32 = at<float>(work, P.V32), *VT32 = at<float>(work, P.VT32), *Vt32 = at<float>(work, P.Vt32);
   float *W32 = at<float>(work, P.W32);
   float *gpart32 = at<float>(work, P.gpart32), *spart = at<float>(work, P.spart);
+  float *gpart32_aux = at<float>(work, P.gpart32_aux);
   float *G32 = at<float>(work, P.G32), *Y32 = at<float>(work, P.Y32);
   float *VS32 = at<float>(work, P.VS32), *TS32 = at<float>(work, P.TS32);
   void *Gb = at<void>(work, P.Gb);
@@ -757,6 +776,24 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     // main stream's short kernels (granting the products exactly what the
     // persistent kernel leaves free measured 12 % slower overall)
     const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2;
+    if constexpr (F32) if (pipe_next) {
+      // FP32 storage (mixed): the BF16 sketch product of block i+1 from the
+      // moved, not yet updated C, beside the panel
+      CHK(hipEventRecord(h->ev_moves, s), "fork event");
+      CHK(hipStreamWaitEvent(aux, h->ev_moves, 0), "auxiliary stream wait");
+      const int64_t mn = mi - bi, nn = ni - bi;
+      if (o->G) {
+        Gn = o->G + goff_of(i + 1);
+      } else {
+        ScopedTimer tg(h, RQRCP_K_SKETCH, 0.0, 8.0 * ks * mn, aux);
+        CHK(launch_sketch(aux, o->seed, i + 1, ks, r0 + bi, mn, G, ks, beside_panel), "sketch");
+        Gn = G;
+      }
+      ScopedTimer ts(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * nn * mn, 4.0 * mn * nn + 2.0 * ks * mn + 8.0 * ks * nn, aux);
+      CHK(launch_g_to_bf16(aux, Gn, ks, ks, mn, Gb, mn, beside_panel), "sketch to BF16");
+      CHK(launch_sample_bf16(aux, ks, nn, mn, Gb, mn, X + bi + bi * lda, lda, spart, Y, ks, beside_panel),
+          "BF16 sketch product of the next block");
+    }
     if constexpr (!F32) if (pipe_next) {
       CHK(hipEventRecord(h->ev_moves, s), "fork event");
       CHK(hipStreamWaitEvent(aux, h->ev_moves, 0), "auxiliary stream wait");
@@ -865,8 +902,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_gemm<float>(s, gw, gpart32), "V^T C");
         }
       }
-      if constexpr (!F32)
-        if (pipe_next) {
+      if (pipe_next) {
           // G_{i+1} V(b_i:, :) on the auxiliary stream after W (beside T^T W;
           // beside W itself it slowed W by a sixth)
           CHK(hipEventRecord(h->ev_w, s), "W event");
@@ -902,6 +938,31 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * nc, 8.0 * (ks * bi + 2.0 * ks * nc + bi * nc));
           GemmF64 g2{false, false, ks, ni - bi, bi, GVb, ks, W2, bi, Y, ks, -1.0, 1.0};
           CHK(launch_gemm_f64(s, g2, gpart), "Y -= (G V) (T^T W)");
+          y_ready = true;
+        } else {
+          // FP32 storage: the update C -= (V T^T) W on the auxiliary stream;
+          // the correction of the next sketch here, in FP64, as
+          // ((G V) T^T) W with W widened from FP32
+          CHK(hipEventRecord(h->ev_vt, s), "update fork event");
+          CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
+          {
+            ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
+                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+            GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
+            gu.max_wg = beside_qrcp;
+            CHK(launch_gemm<float>(aux, gu, gpart32_aux), "C -= (V T^T) W");
+          }
+          CHK(hipEventRecord(h->ev_upd, aux), "update event");
+          upd_pending = true;
+          CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product and G V");
+          ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * nc + 2.0 * ks * bi * bi,
+                         8.0 * (ks * bi + 2.0 * ks * nc + bi * nc) + 4.0 * bi * nc);
+          CHK(launch_copy_f32_f64(s, W32, bi, Wb, bi, bi, ni - bi), "W to FP64");
+          // (G V) T^T into Vt (V T^T went to FP32 on the side stream, joined above)
+          GemmF64 g1{false, true, ks, bi, bi, GVb, ks, Ti, b, Vt, ks, 1.0, 0.0};
+          CHK(launch_gemm_f64(s, g1, gpart), "(G V) T^T");
+          GemmF64 g2{false, false, ks, ni - bi, bi, Vt, ks, Wb, bi, Y, ks, -1.0, 1.0};
+          CHK(launch_gemm_f64(s, g2, gpart), "Y -= ((G V) T^T) W");
           y_ready = true;
         }
       } else {

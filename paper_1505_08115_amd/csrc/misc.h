@@ -63,8 +63,9 @@ inline hipError_t launch_scatter_cols_t(hipStream_t s, const float *a, int64_t l
 
 // mixed-precision sketch (sample_bf16.hip)
 size_t sample_bf16_part_floats(int64_t M, int64_t N, int64_t K);
+// max_wg > 0: at most that many workgroups (beside a persistent kernel)
 hipError_t launch_g_to_bf16(hipStream_t s, const double *G, int64_t ldg, int64_t nsample, int64_t nrows, void *Gb,
-                            int64_t ldgb);
+                            int64_t ldgb, int max_wg = 0);
 hipError_t launch_sample_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const void *Gb, int64_t ldgb,
-                              const float *X, int64_t ldx, float *part, double *Y, int64_t ldy);
+                              const float *X, int64_t ldx, float *part, double *Y, int64_t ldy, int max_wg = 0);
 }  // namespace rq

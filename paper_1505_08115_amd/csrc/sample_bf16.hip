@@ -124,9 +124,12 @@ __global__ __launch_bounds__(256) void g_to_bf16_kernel(const double *__restrict
   }
 }
 
-void plan(int64_t M, int64_t N, int64_t K, int *splits, int64_t *kchunk) {
+// K is split so that the grid fills `slots` workgroups (the 256 CUs, or the
+// cap of a product that runs beside a persistent kernel)
+void plan(int64_t M, int64_t N, int64_t K, int *splits, int64_t *kchunk, int slots = 256) {
   const int64_t tiles = (N + kBN - 1) / kBN;
-  int64_t sp = (256 + tiles - 1) / tiles;
+  int64_t sp = (slots + tiles - 1) / tiles;
+  if (slots < 256) sp = std::max<int64_t>(1, slots / tiles);   // stay within the cap
   const int64_t maxsp = std::max<int64_t>(1, K / (kKS * 8));
   if (sp > maxsp) sp = maxsp;
   if (sp > 64) sp = 64;
@@ -154,22 +157,23 @@ size_t sample_bf16_part_floats(int64_t M, int64_t N, int64_t K) {
 }
 
 hipError_t launch_g_to_bf16(hipStream_t s, const double *G, int64_t ldg, int64_t nsample, int64_t nrows, void *Gb,
-                            int64_t ldgb) {
+                            int64_t ldgb, int max_wg) {
   const int64_t total = nsample * nrows;
   if (total <= 0) return hipSuccess;
   int64_t grid = (total + 255) / 256;
   if (grid > 16384) grid = 16384;
+  if (max_wg > 0 && grid > max_wg) grid = max_wg;
   hipLaunchKernelGGL(g_to_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, s, G, ldg, nsample, nrows,
                      static_cast<__bf16 *>(Gb), ldgb);
   return hipGetLastError();
 }
 
 hipError_t launch_sample_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const void *Gb, int64_t ldgb,
-                              const float *X, int64_t ldx, float *part, double *Y, int64_t ldy) {
+                              const float *X, int64_t ldx, float *part, double *Y, int64_t ldy, int max_wg) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M > kMaxMT * 16) return hipErrorInvalidValue;
   int sp; int64_t kc;
-  plan(M, N, K, &sp, &kc);
+  plan(M, N, K, &sp, &kc, max_wg > 0 && max_wg < 256 ? max_wg : 256);
   dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)sp);
   const __bf16 *G = static_cast<const __bf16 *>(Gb);
   const int mt = (int)((M + 15) / 16);
@@ -184,6 +188,7 @@ hipError_t launch_sample_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, co
   const int64_t MN = M * N;
   int64_t g2 = (MN + 255) / 256;
   if (g2 > 8192) g2 = 8192;
+  if (max_wg > 0 && g2 > max_wg) g2 = max_wg;
   hipLaunchKernelGGL(reduce_to_f64_kernel, dim3((unsigned)g2), dim3(256), 0, s, M, N, sp, part, Y, ldy);
   return hipGetLastError();
 }
