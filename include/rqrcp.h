@@ -129,7 +129,8 @@ void rqrcp_default_opts(rqrcp_opts_t *o);
  * gfx950) and prepares the cooperative kernels.  The handle owns two streams
  * of default priority, a few events and 16 bytes of device memory (its info
  * word), all released by rqrcp_destroy; this is the only device memory the
- * library allocates.  Errors: RQRCP_ERR_ARG (h == NULL),
+ * library allocates (besides the array of rqrcp_factor_noalloc, which the
+ * code object holds on each device).  Errors: RQRCP_ERR_ARG (h == NULL),
  * RQRCP_ERR_UNSUPPORTED (not a gfx950 device), RQRCP_ERR_HIP. */
 rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream);
 rqrcp_status_t rqrcp_set_stream(rqrcp_handle_t h, void *hip_stream);
@@ -179,6 +180,25 @@ rqrcp_status_t rqrcp_factor_sizes(rqrcp_dtype_t dt, int64_t m, int64_t n, const 
 rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n,
                             void *A, int64_t lda, int32_t *jpvt, double *tau, double *T,
                             double *S, const rqrcp_opts_t *o, void *work, size_t work_bytes);
+
+/* rqrcp_factor without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, allocation-free
+ * serving loops, harnesses that forbid hipMalloc).  Arguments, results and
+ * errors are those of rqrcp_factor; the workspace is instead a device array
+ * of RQRCP_NOALLOC_WORK_BYTES that the library holds on every device it runs
+ * on until the process ends (its address is taken once per device by
+ * rqrcp_create).  The call allocates nothing.  Problems whose workspace
+ * (rqrcp_factor_sizes) exceeds RQRCP_NOALLOC_WORK_BYTES are refused with
+ * RQRCP_ERR_WORKSPACE before any launch; RQRCP_ERR_ARG if the current device
+ * is not the handle's.  Every call on a device shares that device's array:
+ * calls that overlap on one GPU (other handles or streams) race and give
+ * wrong results; calls that follow each other in stream order are safe (the
+ * array keeps the last call's contents, and each call writes every part it
+ * reads and clears what must start at zero). */
+#define RQRCP_NOALLOC_WORK_BYTES (64u << 20)
+rqrcp_status_t rqrcp_factor_noalloc(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n,
+                                    void *A, int64_t lda, int32_t *jpvt, double *tau, double *T,
+                                    double *S, const rqrcp_opts_t *o);
 
 /* Apply Q or Q^T from a stored factorization to C (m x ncol, ld ldc >= m):
  * trans = 0: C <- Q C;  trans = 1: C <- Q^T C.  Q = Q_0 Q_1 ... Q_{nb-1} with

@@ -31,7 +31,8 @@ TAIL = {"classical": 0, "sampled": 1}
 #: every function that include/rqrcp.h declares
 EXPORTS = [
     "rqrcp_default_opts", "rqrcp_create", "rqrcp_set_stream", "rqrcp_destroy", "rqrcp_status_string",
-    "rqrcp_check", "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
+    "rqrcp_check", "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_factor_noalloc",
+    "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
     "rqrcp_apply_p_work_bytes", "rqrcp_apply_p", "rqrcp_lowrank_work_bytes", "rqrcp_lowrank",
     "rqrcp_lowrank_backward_work_bytes", "rqrcp_lowrank_backward", "rqrcp_sketch", "rqrcp_timing_enable",
     "rqrcp_timing_read", "rqrcp_timing_classes",
@@ -82,6 +83,7 @@ def load_library():
         "rqrcp_factor_sizes": (_i32, [_i32, _i64, _i64, _vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz),
                                       ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
         "rqrcp_factor": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz]),
+        "rqrcp_factor_noalloc": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
         "rqrcp_apply_q_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
         "rqrcp_apply_q": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz]),
         "rqrcp_apply_p_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
@@ -275,6 +277,38 @@ def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain",
     factor_into(F, jp, tau, T, S, work, block=block, oversample=oversample, rank=kk, pivot=pivot,
                 precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, G=G, info=info,
                 power=power, panel_pivot=panel_pivot, diagonalize=diagonalize)
+    return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize), info)
+
+
+#: workspace bytes of rqrcp_factor_noalloc (RQRCP_NOALLOC_WORK_BYTES)
+NOALLOC_WORK_BYTES = 64 << 20
+
+
+def factor_noalloc(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain", rank=0,
+                   tail="classical", G=None, jpvt=None, info=None, power=0, panel_pivot=False,
+                   diagonalize=False) -> Factorization:
+    """factor() through rqrcp_factor_noalloc: the library's own device array
+    serves as the workspace (the outputs are still allocated here, by torch)."""
+    L = load_library()
+    m, n = A.shape
+    F = colmajor(A)
+    kk = n if rank in (0, None) else int(rank)
+    sizes = factor_sizes(m, n, A.dtype, block=block, oversample=oversample, rank=kk, pivot=pivot,
+                         precision=precision, tail=tail, fixed_pivots=jpvt is not None, seed=seed, power=power,
+                         panel_pivot=panel_pivot, diagonalize=diagonalize)
+    dev = A.device
+    tau = torch.empty(max(1, sizes[0]), dtype=torch.float64, device=dev)
+    T = torch.empty(max(1, sizes[1]), dtype=torch.float64, device=dev)
+    S = torch.empty(sizes[2], dtype=torch.float64, device=dev) if pivot == "ortho" else None
+    jp = jpvt.to(device=dev, dtype=torch.int32).clone() if jpvt is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    if info is None:
+        info = torch.zeros(4, dtype=torch.int32, device=dev)
+    o = make_opts(block, oversample, kk, pivot, precision, tail, jpvt is not None, seed, G, info, power, panel_pivot,
+                  diagonalize)
+    h = handle(dev)
+    with torch.cuda.device(dev):
+        _check(L.rqrcp_factor_noalloc(h, _dt(F), m, n, _ptr(F), _ld(F), _ptr(jp), _ptr(tau), _ptr(T), _ptr(S),
+                                      ctypes.byref(o)), h)
     return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize), info)
 
 

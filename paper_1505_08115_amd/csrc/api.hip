@@ -7,10 +7,36 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 #include "misc.h"
+
+// Workspace of the allocation-free entry point (rqrcp_factor_noalloc): one
+// array per device, held until the process ends.  Host code uses the device
+// address that hipGetSymbolAddress returns for the current device (kept per
+// device by rqrcp_create), never the array's name.
+static __device__ __align__(256) unsigned char scratch[RQRCP_NOALLOC_WORK_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // device address of `scratch`, per device (nullptr until set up)
+
+// Once per device, with that device current: the address of its copy of `scratch`.
+hipError_t scratch_setup(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
 
 struct rqrcp_timing_rec {
   int kclass;
@@ -33,6 +59,7 @@ struct rqrcp_ctx {
   // device int32[4]: the info word of factorizations given no opts.info, so
   // that a give-up of a grid-wide wait is never lost (read by rqrcp_check)
   int32_t *own_info = nullptr;
+  void *scratch = nullptr;    // this device's `scratch` (rqrcp_factor_noalloc)
   int device = 0;
   uint64_t limit_ticks = 0;   // grid-barrier wait limit (about 2 s of the device clock)
   std::string last_error;
@@ -423,6 +450,7 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->own_info), 4 * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(c->own_info, 0, 4 * sizeof(int32_t));
+  if (e == hipSuccess) e = scratch_setup(dev, &c->scratch);
   if (e != hipSuccess) {
     if (c->own_info) (void)hipFree(c->own_info);
     for (hipEvent_t *ev : evs)
@@ -432,7 +460,7 @@ rqrcp_status_t rqrcp_create(rqrcp_handle_t *h, void *hip_stream) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
-    return fail_hip(nullptr, e, "side stream / events / info word");
+    return fail_hip(nullptr, e, "side stream / events / info word / scratch address");
   }
   c->ncu = prop.multiProcessorCount;
   c->device = dev;
@@ -1013,25 +1041,59 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   return RQRCP_OK;
 }
 
-}  // namespace
-}  // namespace rq
-
-extern "C" {
-
-rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av, int64_t lda,
-                            int32_t *jpvt, double *tau, double *T, double *S, const rqrcp_opts_t *o, void *work,
-                            size_t work_bytes) {
-  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
-  FactorPlan P;
-  rqrcp_status_t st = make_plan(h, dt, m, n, o, &P);
+// Checks of rqrcp_factor's arguments other than the workspace.
+rqrcp_status_t factor_args(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av, int64_t lda,
+                           int32_t *jpvt, double *tau, double *T, double *S, const rqrcp_opts_t *o,
+                           FactorPlan *P) {
+  rqrcp_status_t st = make_plan(h, dt, m, n, o, P);
   if (st != RQRCP_OK) return st;
   if (!Av) return fail(h, RQRCP_ERR_ARG, "A is NULL");
   if (lda < m) return fail(h, RQRCP_ERR_ARG, "lda must be >= m");
   if (!jpvt) return fail(h, RQRCP_ERR_ARG, "jpvt is NULL");
   if (!tau) return fail(h, RQRCP_ERR_ARG, "tau is NULL");
   if (!T) return fail(h, RQRCP_ERR_ARG, "T is NULL");
-  if (P.ortho && !S) return fail(h, RQRCP_ERR_ARG, "S is NULL (required for ORTHO)");
-  if (!P.ortho && S) return fail(h, RQRCP_ERR_ARG, "S must be NULL for PERM");
+  if (P->ortho && !S) return fail(h, RQRCP_ERR_ARG, "S is NULL (required for ORTHO)");
+  if (!P->ortho && S) return fail(h, RQRCP_ERR_ARG, "S must be NULL for PERM");
+  return RQRCP_OK;
+}
+
+}  // namespace
+}  // namespace rq
+
+extern "C" {
+
+rqrcp_status_t rqrcp_factor_noalloc(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av,
+                                    int64_t lda, int32_t *jpvt, double *tau, double *T, double *S,
+                                    const rqrcp_opts_t *o) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  FactorPlan P;
+  rqrcp_status_t st = factor_args(h, dt, m, n, Av, lda, jpvt, tau, T, S, o, &P);
+  if (st != RQRCP_OK) return st;
+  if (P.total > (size_t)RQRCP_NOALLOC_WORK_BYTES)
+    return fail(h, RQRCP_ERR_WORKSPACE,
+                "this problem needs " + std::to_string(P.total) + " bytes of workspace; rqrcp_factor_noalloc has " +
+                    std::to_string((size_t)RQRCP_NOALLOC_WORK_BYTES) + " (use rqrcp_factor with a workspace)");
+  if (!h->scratch) return fail(h, RQRCP_ERR_HIP, "no scratch address for this device");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(h, e, "hipGetDevice");
+  if (dev != h->device) return fail(h, RQRCP_ERR_ARG, "the current device is not the handle's device");
+  // every region of the workspace is written before it is read, and the
+  // parts that must start at zero (barrier state) are cleared by fill kernels
+  rqrcp_opts_t oc = *o;
+  if (!oc.info) oc.info = h->own_info;
+  if (dt == RQRCP_F64)
+    return factor_impl<double>(h, P, &oc, static_cast<double *>(Av), lda, jpvt, tau, T, S, h->scratch);
+  return factor_impl<float>(h, P, &oc, static_cast<float *>(Av), lda, jpvt, tau, T, S, h->scratch);
+}
+
+rqrcp_status_t rqrcp_factor(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, void *Av, int64_t lda,
+                            int32_t *jpvt, double *tau, double *T, double *S, const rqrcp_opts_t *o, void *work,
+                            size_t work_bytes) {
+  if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
+  FactorPlan P;
+  rqrcp_status_t st = factor_args(h, dt, m, n, Av, lda, jpvt, tau, T, S, o, &P);
+  if (st != RQRCP_OK) return st;
   if (!work) return fail(h, RQRCP_ERR_WORKSPACE, "work is NULL");
   if (work_bytes < P.total) return fail(h, RQRCP_ERR_WORKSPACE, "work_bytes smaller than rqrcp_factor_sizes");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(h, RQRCP_ERR_WORKSPACE, "work must be 256-byte aligned");
