@@ -119,6 +119,14 @@ size_t gemm_part_doubles(int64_t M, int64_t N, int64_t K) {
   return sp > 1 ? (size_t)sp * M * N : 0;
 }
 
+// S = V^T V (cols x cols, ld cols) for the T factor of the reflectors in the
+// explicit unit-lower V (rows x cols, ld ldv).
+hipError_t launch_gram(hipStream_t s, const double *V, int64_t ldv, int64_t rows, int64_t cols, double *S,
+                       double *part) {
+  GemmF64 g{true, false, cols, cols, rows, V, ldv, V, ldv, S, cols, 1.0, 0.0};
+  return launch_gemm_f64(s, g, part);
+}
+
 // The same for an FP32 product (the all-rows engine takes more rows in FP32).
 size_t gemm_part_floats(int64_t M, int64_t N, int64_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
@@ -215,6 +223,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     if (pn == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "panel too large for the panel kernel");
     ppart = std::max(ppart, panel_part_doubles(pn, (int)bi));
     vtp = std::max(vtp, gemm_part_doubles(mi, bi, bi));
+    vtp = std::max(vtp, gemm_part_doubles(bi, bi, mi));      // V^T V beside W
+    gpart = std::max(gpart, gemm_part_doubles(bi, bi, mi));  // V^T V of the last block
     if (P.diag) {   // U'^T C and A12 V' run on the side stream as well
       vtp = std::max(vtp, gemm_part_doubles(bi, ni - bi, bi));
       vtp = std::max(vtp, gemm_part_doubles(r0, bi, bi));
@@ -242,6 +252,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
           const int pn2 = panel_config(ni, (int)bi, &rpw);
           if (pn2 == 0) return fail(h, RQRCP_ERR_UNSUPPORTED, "sketch too large for the panel kernel");
           ppart = std::max(ppart, panel_part_doubles(pn2, (int)bi));
+          gpart = std::max(gpart, gemm_part_doubles(bi, bi, ni));   // V_S^T V_S
           gpart = std::max(gpart, gemm_part_doubles(m, bi, ni));
           gpart = std::max(gpart, gemm_part_doubles(m, ni, bi));
         } else {
@@ -767,10 +778,11 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_transpose(s, Y, ks, YT, ni, bi, ni), "transpose sketch");
           PanelQR pq{};
           pq.P = YT; pq.ldp = ni; pq.mi = ni; pq.nb = (int)bi;
-          pq.tau = tauS + i * b; pq.V = VS; pq.ldv = ni; pq.S = Sg;
+          pq.tau = tauS + i * b; pq.V = VS; pq.ldv = ni;
           pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
           next_slot(&pq.bar, &pq.abort_flag);
           CHK(launch_panel_qr(s, pq), "QR of the sketch");
+          CHK(launch_gram(s, VS, ni, ni, bi, Sg, gpart), "V_S^T V_S");
           CHK(launch_wy_t(s, (int)bi, tauS + i * b, Sg, TSi, b), "T of the sketch reflectors");
           // A(0:m, r0:n) <- A(0:m, r0:n) (I - VS TS VS^T), all m rows
           CHK(join_diag(), "wait for the previous block's diagonalisation");
@@ -853,7 +865,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         CHK(launch_copy2d(s, X, lda, Pc, mi, mi, bi), "save the panel");
         PanelQR pq{};
         pq.P = X; pq.ldp = lda; pq.mi = mi; pq.nb = (int)bi;
-        pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+        pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi;
         pq.VT = nullptr; pq.ldvt = b;
         pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
         next_slot(&pq.bar, &pq.abort_flag);
@@ -880,7 +892,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         pq.P = X; pq.ldp = lda;
       }
       pq.mi = mi; pq.nb = (int)bi;
-      pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi; pq.S = Sg;
+      pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi;
       pq.VT = VT; pq.ldvt = b;
       pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
       next_slot(&pq.bar, &pq.abort_flag);
@@ -890,6 +902,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     double *Ti = Tout + (size_t)i * b * b;
     if (ni <= bi) {
       ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
+      CHK(launch_gram(s, Vb, mi, mi, bi, Sg, gpart), "V^T V");
       CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
     } else {
       // C <- (I - V T V^T)^T C = C - (V T^T) (V^T C)   (Section 5.1).  W = V^T C
@@ -907,6 +920,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
       {
         ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
+        CHK(launch_gram(h->side, Vb, mi, mi, bi, Sg, vtpart), "V^T V");
         CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
       }
       if (!reassoc) {

@@ -265,7 +265,6 @@ struct PanelQR {
   double *tau;            // [nb]
   double *V; int64_t ldv; // explicit unit-lower V (mi x nb)
   double *VT; int64_t ldvt;   // NULL, or V^T (nb x mi) written as well
-  double *S;              // nb x nb Gram V^T V (column j valid for rows <= j)
   double *part;           // partial sums, panel_part_doubles()
   double *red;            // reduced sums, nb * kPanelW doubles
   unsigned *bar;
@@ -279,7 +278,8 @@ int panel_config(int64_t mi, int nb, int *rpw);   // workgroups (0 = unsupported
 size_t panel_part_doubles(int nwg, int nb);
 hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p);
 
-// T of the compact WY form from tau and the Gram matrix S = V^T V.
+// T of the compact WY form from tau and the Gram matrix S = V^T V (nb x nb,
+// ld nb; column j is read for rows <= j).
 hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt);
 
 // SVD of the nb x nb upper triangle of F (ld ldf, nb <= svd_small_max_block()):

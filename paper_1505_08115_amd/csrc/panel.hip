@@ -15,10 +15,12 @@
 //     follows from the reduced sums alone: v^T x_c = (g_c - beta x_c(j)) /
 //     (alpha - beta).  Degenerate columns follow the conventions of the
 //     oracle: tau = 0 for a zero column or a column of length one.
-//   * after a slab: the partial products V_s^T [V_0 .. V_s | A_rest] are
-//     reduce-scattered (two barriers); they give the Gram rows needed for T
-//     and W = V_s^T A_rest, which updates the rest of the panel as
-//     A_rest <- A_rest - V_s (T_s^T W).
+//   * after a slab: the partial products V_s^T [V_s | A_rest] are
+//     reduce-scattered (two barriers); they give the slab's Gram block
+//     V_s^T V_s for its T_s and W = V_s^T A_rest, which updates the rest of
+//     the panel as A_rest <- A_rest - V_s (T_s^T W).  (The Gram matrix V^T V
+//     of the whole panel, which the T factor needs, is a product of the
+//     explicit V formed outside the kernel.)
 #include <type_traits>
 
 #include "common.h"
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   const int rpw4 = (rpw + 3) & ~3;           // rows padded to the MFMA K step
   const int ldx = rpw4 + 1;                 // odd stride: the 16 lanes of a fragment hit distinct banks
   double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
-  double *Wp = X + (size_t)W * ldx;         // W x nb    reduced V_s^T [V_0..V_s | A_rest], row t at Wp + t*nb
+  double *Wp = X + (size_t)W * ldx;         // W x nb    reduced V_s^T [V_s | A_rest], row t at Wp + t*nb (columns >= cs)
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
   double *sc = Ts + W * W;                  // 640       reduction scratch
   double *taus = sc + 640;                  // W
@@ -320,19 +322,20 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       X[c * ldx + r] = rg > jc ? x : (rg == jc ? 1.0 : 0.0);
     }
     __syncthreads();
-    // partial products V_s^T Z over own rows, Z = [V_0..V_s | A_rest], on the
-    // matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j]
-    // from lane j + 16k, D[i][j] in lane j + 16 (i%4), register i/4).  Wave w
-    // owns the 16-column blocks w, w+4, ... of the 32 x nb output; its lanes
-    // load Z straight from V (every column left of A_rest, the slab's
-    // explicit V written above included) or P (A_rest), up to 32 loads in
-    // flight; V_s^T comes from LDS.  Batches have a fixed size (32, 16, ...,
+    // partial products V_s^T Z over own rows, Z = [V_s | A_rest] (columns
+    // cs .. nb), on the matrix cores (v_mfma_f64_16x16x4: A[i][k] from lane
+    // i + 16k, B[k][j] from lane j + 16k, D[i][j] in lane j + 16 (i%4),
+    // register i/4).  Wave w owns the 16-column blocks cs/16 + w, + 4, ... of
+    // the 32 x (nb - cs) output; its lanes load Z straight from V (the slab's
+    // explicit V written above) or P (A_rest), up to 32 loads in flight;
+    // V_s^T comes from LDS.  Batches have a fixed size (32, 16, ...,
     // 1 steps of K), so the loads and MFMAs of a batch are straight-line code.
+    const int nz = nb - cs;   // columns of Z = [V_s | A_rest]
     double *mypart = part_up + (size_t)wg * W * nb;
     const int lane = t & 63, wave = t >> 6, li = lane & 15, lk = lane >> 4;
     {
       const int nbk = (nb + 15) / 16, KS = rpw4 / 4, nr1 = max(nrow - 1, 0);
-      for (int jb = wave; jb < nbk; jb += kPThreads / 64) {
+      for (int jb = cs / 16 + wave; jb < nbk; jb += kPThreads / 64) {
         const int col = 16 * jb + li;
         // columns past nb load column nb - 1 (their outputs are never stored);
         // a workgroup without rows loads row 0 of P (its X is all zero)
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int i = 16 * a + 4 * q + lk;
-            if (i < ws && col < nb) st_agent(mypart + i * nb + col, acc[a][0][q] + acc[a][1][q]);
+            if (i < ws && col < nb) st_agent(mypart + i * nz + (col - cs), acc[a][0][q] + acc[a][1][q]);
           }
       }
     }
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       // workgroups' partials; G threads share an element, thread g taking a
       // contiguous range of workgroups with its loads issued 8 at a time, and
       // the G range sums are added in range order (a fixed order)
-      const int E = ws * nb;
+      const int E = ws * nz;
       const int per = (E + nwg - 1) / nwg;
       const int beg = wg * per, end = min(E, beg + per);
       const int G = per >= kPThreads ? 1 : (per >= kPThreads / 2 ? 2 : (per >= kPThreads / 4 ? 4 : 8));
@@ -414,28 +417,22 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     }
     ok = grid_sync(gb, gen, true, true);
     if (!ok) break;
-    // the reduced rows V_s^T [V_0 .. V_s | A_rest] -> LDS (row tt at Wp + tt*nb), 8 loads in flight
-    for (int base = 0; base < ws * nb; base += 8 * kPThreads) {
+    // the reduced rows V_s^T [V_s | A_rest] -> LDS (row tt at Wp + tt*nb,
+    // columns cs .. nb), 8 loads in flight
+    for (int base = 0; base < ws * nz; base += 8 * kPThreads) {
       double x[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = base + t + u * kPThreads;
-        x[u] = idx < ws * nb ? ld_agent(p.red + idx) : 0.0;
+        x[u] = idx < ws * nz ? ld_agent(p.red + idx) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = base + t + u * kPThreads;
-        if (idx < ws * nb) Wp[idx] = x[u];
+        if (idx < ws * nz) Wp[(idx / nz) * nb + cs + idx % nz] = x[u];
       }
     }
     for (int idx = ws * nb + t; idx < W * nb; idx += kPThreads) Wp[idx] = 0.0;   // rows ws .. W of a ragged slab
-    __syncthreads();
-    // Gram rows -> S (column j = cs + tt holds v_q^T v_j for q < cs + ws)
-    if (wg == 0)
-      for (int idx = t; idx < ws * (cs + ws); idx += kPThreads) {
-        const int tt = idx / (cs + ws), q = idx % (cs + ws);
-        p.S[q + (int64_t)(cs + tt) * nb] = Wp[tt * nb + q];
-      }
     // T_s by the recurrence T(r, tt) = -tau_tt sum_{r<=u<tt} T(r, u) v_u^T v_tt,
     // which involves only row r.  Eight lanes share a row (all 256 threads:
     // 32 rows x 8): lane `part` keeps T(r, u) for u = part + 8i in registers

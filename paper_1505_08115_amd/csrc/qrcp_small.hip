@@ -40,6 +40,11 @@ constexpr size_t kLdsDoubles = 20480 - 256;   // 160 KiB minus room for static s
 __device__ __forceinline__ bool better(double v1, int p1, double v2, int p2) {
   return v1 > v2 || (v1 == v2 && p1 < p2);
 }
+// The same without branches (for arg-max exchanges between lanes and for
+// loops whose loads should all issue before the comparisons).
+__device__ __forceinline__ int better_bits(double v1, int p1, double v2, int p2) {
+  return (int)(v1 > v2) | ((int)(v1 == v2) & (int)(p1 < p2));
+}
 
 __device__ void flag_nonfinite(int32_t *info, int block_index) {
   if (!info) return;
@@ -53,7 +58,10 @@ template <int CTRL>
 __device__ __forceinline__ void argmax_dpp(double &v, int &p, int &i) {
   const double v2 = dpp_mov<CTRL>(v);
   const int p2 = dpp_mov<CTRL>(p), i2 = dpp_mov<CTRL>(i);
-  if (better(v2, p2, v, p)) { v = v2; p = p2; i = i2; }
+  const int take = better_bits(v2, p2, v, p);   // selects, no branch
+  v = take ? v2 : v;
+  p = take ? p2 : p;
+  i = take ? i2 : i;
 }
 // The same across lanes i and i ^ SPAN (16 or 32): both lanes see the pair
 // in the same order and pick the same member.
@@ -64,7 +72,7 @@ __device__ __forceinline__ void argmax_span(double &v, int &p, int &i) {
   lane_pair<SPAN>(v, vl, vh);
   lane_pair<SPAN>(p, pl, ph);
   lane_pair<SPAN>(i, il, ih);
-  const bool up = better(vh, ph, vl, pl);
+  const int up = better_bits(vh, ph, vl, pl);
   v = up ? vh : vl;
   p = up ? ph : pl;
   i = up ? ih : il;
@@ -338,9 +346,10 @@ __global__ __launch_bounds__(kQThreads) void qrcp_reg_kernel(QrcpSmall q, GridBa
 #pragma unroll
       for (int u = 0; u < 4; ++u) {           // gi packs (workgroup << 16) | column
         const int w2 = lane + 64 * u;
-        if (w2 < nwg && rc[u] >= 0.0 && better(rv[u], (int)rp[u], gv, gp)) {
-          gv = rv[u]; gp = (int)rp[u]; gi = (w2 << 16) | (int)rc[u];
-        }
+        const int take = (int)(w2 < nwg) & (int)(rc[u] >= 0.0) & better_bits(rv[u], (int)rp[u], gv, gp);
+        gv = take ? rv[u] : gv;
+        gp = take ? (int)rp[u] : gp;
+        gi = take ? ((w2 << 16) | (int)rc[u]) : gi;
       }
       wave_argmax(gv, gp, gi);
       gp = lane0(gp);
