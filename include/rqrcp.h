@@ -115,9 +115,10 @@ typedef struct {
                         /* Q = prod_i diag(I, (I - V_i T_i V_i^T) diag(U'_i, I)) and   */
                         /* P = prod_i diag(I, S_i) diag(I, V'_i, I); U'_i, V'_i (b x b, */
                         /* ld b) follow the T_S blocks in S (see rqrcp_factor).  FP64, */
-                        /* ORTHO and b <= 64 only (else RQRCP_ERR_UNSUPPORTED).        */
-                        /* rqrcp_apply_q/_apply_p/_lowrank/_lowrank_backward do not    */
-                        /* read U' or V': they cover factorizations without it         */
+                        /* ORTHO and b <= 256 only (else RQRCP_ERR_UNSUPPORTED).       */
+                        /* rqrcp_apply_q (its UV argument), rqrcp_apply_p and          */
+                        /* rqrcp_lowrank (their diagonalized flag) apply U' and V';    */
+                        /* rqrcp_lowrank_backward covers the permutation form only     */
 } rqrcp_opts_t;
 
 /* Default options: b = 128, p = 10, full rank, permutation, plain, classical
@@ -205,7 +206,11 @@ rqrcp_status_t rqrcp_factor_noalloc(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t 
  * Q_i = diag(I_{i*b}, I - V_i T_i V_i^T) (Fig. 3's accumulation of Q-tilde,
  * applied in WY form as Section 5.1 asks).  VR, ldvr: the factored A (only
  * the Householder vectors below the diagonal of its first k columns are
- * read); T as written by rqrcp_factor; k, b as used there.  C has the storage
+ * read); T as written by rqrcp_factor; k, b as used there.  UV: NULL, or for
+ * a diagonalised factorization (Section 6.2) its U'/V' blocks in S (at
+ * element rqrcp_diag_offset(n, k, b) of S): then every Q_i is followed by
+ * diag(I_{i*b}, U'_i, I) and Q = (Q_0 ... Q_{nb-1}) diag(U'_0, U'_1, ...),
+ * since U'_i acts on rows that later blocks leave alone.  C has the storage
  * type dt; with dt = F32 the operands are widened to FP64 in the workspace,
  * the products run in FP64 and C is rounded back to FP32.  work: at least
  * rqrcp_apply_q_work_bytes bytes.
@@ -213,30 +218,40 @@ rqrcp_status_t rqrcp_factor_noalloc(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t 
 size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t k, int64_t b, int64_t ncol);
 rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t m, int64_t k,
                              int64_t b, const void *VR, int64_t ldvr, const double *T,
-                             int64_t ncol, void *C, int64_t ldc, void *work, size_t work_bytes);
+                             const double *UV, int64_t ncol, void *C, int64_t ldc, void *work,
+                             size_t work_bytes);
+/* Offset (in doubles) of the U'_0 V'_0 U'_1 V'_1 ... blocks inside S for a
+ * diagonalised factorization of n columns, rank k, block b (host only). */
+size_t rqrcp_diag_offset(int64_t n, int64_t k, int64_t b);
 
 /* Apply P or P^T from the right to C (nrow x n, ld ldc >= nrow):
  * trans = 0: C <- C P;  trans = 1: C <- C P^T.  PERM (S == NULL): a column
  * permutation by jpvt ((C P)(:, j) = C(:, jpvt[j])).  ORTHO: the product of
- * the S blocks (k, b as in the factorization).  C has the storage type dt
- * (F32: computed in FP64 on a widened copy).  work: at least
- * rqrcp_apply_p_work_bytes bytes. */
+ * the S blocks (k, b as in the factorization); diagonalized = 1 (a
+ * diagonalised factorization, Section 6.2): each S_i is followed by
+ * diag(I_{i*b}, V'_i, I), so P = (S_0 S_1 ...) diag(V'_0, V'_1, ...) with the
+ * V'_i read from S.  C has the storage type dt (F32: computed in FP64 on a
+ * widened copy).  work: at least rqrcp_apply_p_work_bytes bytes.
+ * Errors: RQRCP_ERR_ARG (also diagonalized without S), RQRCP_ERR_WORKSPACE,
+ * RQRCP_ERR_HIP. */
 size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t dt, int64_t nrow, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t nrow, int64_t n,
-                             int64_t k, int64_t b, const int32_t *jpvt, const double *S, void *C,
-                             int64_t ldc, void *work, size_t work_bytes);
+                             int64_t k, int64_t b, const int32_t *jpvt, const double *S,
+                             int diagonalized, void *C, int64_t ldc, void *work, size_t work_bytes);
 
 /* Truncated factorization A_k = Q(:, 0:k) R(0:k, :) P^* (Section 7's e_k
  * definition; Section 6.1 for its error ||R_22||).  Inputs as written by
  * rqrcp_factor with rank kf >= k (VR, ldvr, jpvt, T, S); kf fixes how many
- * blocks of T and S exist (P is the product of all kf/b S blocks).  Ak (out)
+ * blocks of T and S exist (P is the product of all kf/b S blocks);
+ * diagonalized = 1 reads U' and V' from S as rqrcp_apply_q and
+ * rqrcp_apply_p describe.  Ak (out)
  * m x n, ld ldak >= m, type dt (F32: VR is widened to FP64, the products run
  * in FP64 and A_k is rounded to FP32).  work: at least rqrcp_lowrank_work_bytes. */
 size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k,
                              int64_t kf, int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt,
-                             const double *T, const double *S, void *Ak, int64_t ldak, void *work,
-                             size_t work_bytes);
+                             const double *T, const double *S, int diagonalized, void *Ak, int64_t ldak,
+                             void *work, size_t work_bytes);
 
 /* Gradient of a loss L(A_k) through the truncated factorization with the
  * pivots held fixed (an addition to the paper).  With Q_k = Q(:, 0:k),

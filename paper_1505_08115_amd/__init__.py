@@ -32,7 +32,7 @@ TAIL = {"classical": 0, "sampled": 1}
 EXPORTS = [
     "rqrcp_default_opts", "rqrcp_create", "rqrcp_set_stream", "rqrcp_destroy", "rqrcp_status_string",
     "rqrcp_check", "rqrcp_last_error", "rqrcp_factor_sizes", "rqrcp_factor", "rqrcp_factor_noalloc",
-    "rqrcp_apply_q_work_bytes", "rqrcp_apply_q",
+    "rqrcp_apply_q_work_bytes", "rqrcp_apply_q", "rqrcp_diag_offset",
     "rqrcp_apply_p_work_bytes", "rqrcp_apply_p", "rqrcp_lowrank_work_bytes", "rqrcp_lowrank",
     "rqrcp_lowrank_backward_work_bytes", "rqrcp_lowrank_backward", "rqrcp_sketch", "rqrcp_timing_enable",
     "rqrcp_timing_read", "rqrcp_timing_classes",
@@ -85,12 +85,14 @@ def load_library():
         "rqrcp_factor": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz]),
         "rqrcp_factor_noalloc": (_i32, [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
         "rqrcp_apply_q_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
-        "rqrcp_apply_q": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz]),
-        "rqrcp_apply_p_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
-        "rqrcp_apply_p": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _sz]),
-        "rqrcp_lowrank_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
-        "rqrcp_lowrank": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp,
+        "rqrcp_apply_q": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
                                  _sz]),
+        "rqrcp_diag_offset": (_sz, [_i64, _i64, _i64]),
+        "rqrcp_apply_p_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
+        "rqrcp_apply_p": (_i32, [_vp, _i32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _i64, _vp, _sz]),
+        "rqrcp_lowrank_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
+        "rqrcp_lowrank": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _vp,
+                                 _i64, _vp, _sz]),
         "rqrcp_lowrank_backward_work_bytes": (_sz, [_i32, _i64, _i64, _i64, _i64]),
         "rqrcp_lowrank_backward": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                                           _vp, _i64, _vp, _i64, _vp, _sz]),
@@ -312,15 +314,16 @@ def factor_noalloc(A, block=128, oversample=10, seed=0, pivot="perm", precision=
     return Factorization(F, jp, tau, T, S, int(block), kk, pivot, bool(diagonalize), info)
 
 
-def _plain(Fz):
-    if Fz.diagonalized:
-        raise RqrcpError(4, "Q and P of a diagonalised factorization carry U' and V' (rqrcp_apply_q, "
-                            "rqrcp_apply_p and rqrcp_lowrank cover factorizations without them)")
+def _uv_ptr(Fz):
+    """Device address of the U'/V' blocks of a diagonalised factorization, or None."""
+    if not Fz.diagonalized:
+        return None
+    off = load_library().rqrcp_diag_offset(Fz.F.shape[1], Fz.rank, Fz.block)
+    return Fz.S.data_ptr() + 8 * off
 
 
 def apply_q(Fz: Factorization, C, trans=False):
     """Q C or Q^T C in place on a column-major C; returns C."""
-    _plain(Fz)
     L = load_library()
     m, k = Fz.F.shape[0], Fz.rank
     dt = _dt(C)
@@ -328,13 +331,12 @@ def apply_q(Fz: Factorization, C, trans=False):
     work = torch.empty(max(wb, 256), dtype=torch.uint8, device=C.device)
     h = handle(C.device)
     _check(L.rqrcp_apply_q(h, dt, 1 if trans else 0, m, k, Fz.block, _ptr(Fz.F), _ld(Fz.F), _ptr(Fz.T),
-                           C.shape[1], _ptr(C), _ld(C), _ptr(work), work.numel()), h)
+                           _uv_ptr(Fz), C.shape[1], _ptr(C), _ld(C), _ptr(work), work.numel()), h)
     return C
 
 
 def apply_p(Fz: Factorization, C, trans=False):
     """C P or C P^T in place on a column-major C (nrow x n); returns C."""
-    _plain(Fz)
     L = load_library()
     n, k = Fz.F.shape[1], Fz.rank
     dt = _dt(C)
@@ -342,13 +344,12 @@ def apply_p(Fz: Factorization, C, trans=False):
     work = torch.empty(max(wb, 256), dtype=torch.uint8, device=C.device)
     h = handle(C.device)
     _check(L.rqrcp_apply_p(h, dt, 1 if trans else 0, C.shape[0], n, k, Fz.block, _ptr(Fz.jpvt), _ptr(Fz.S),
-                           _ptr(C), _ld(C), _ptr(work), work.numel()), h)
+                           1 if Fz.diagonalized else 0, _ptr(C), _ld(C), _ptr(work), work.numel()), h)
     return C
 
 
 def lowrank(Fz: Factorization, k=None):
     """A_k = Q(:, 0:k) R(0:k, :) P^* as a new column-major tensor."""
-    _plain(Fz)
     L = load_library()
     m, n = Fz.F.shape
     k = Fz.rank if k is None else int(k)
@@ -358,14 +359,14 @@ def lowrank(Fz: Factorization, k=None):
     work = torch.empty(max(wb, 256), dtype=torch.uint8, device=Ak.device)
     h = handle(Ak.device)
     _check(L.rqrcp_lowrank(h, dt, m, n, k, Fz.rank, Fz.block, _ptr(Fz.F), _ld(Fz.F), _ptr(Fz.jpvt), _ptr(Fz.T),
-                           _ptr(Fz.S), _ptr(Ak), _ld(Ak), _ptr(work), work.numel()), h)
+                           _ptr(Fz.S), 1 if Fz.diagonalized else 0, _ptr(Ak), _ld(Ak), _ptr(work), work.numel()),
+           h)
     return Ak
 
 
 def lowrank_backward(A, Fz: Factorization, dAk, k=None):
     """Gradient w.r.t. A of a loss of A_k, pivots held fixed (column-major in/out).
     Permutation form only (the library's backward reads jpvt, not S)."""
-    _plain(Fz)
     if Fz.pivot != "perm":
         raise RqrcpError(RQRCP_ERR_UNSUPPORTED, "lowrank_backward covers the permutation form only")
     L = load_library()

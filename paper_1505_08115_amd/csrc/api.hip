@@ -160,6 +160,7 @@ struct FactorPlan {
   size_t W2 = 0;       // T^T W (overlapped schedule)
   size_t Z = 0;        // Y X^T of the power iteration
   size_t Pc = 0, Rp = 0;   // saved panel and its R' (in-block pivoting)
+  size_t svdw = 0;         // working columns of the SVD of blocks above 64 columns
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -194,7 +195,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->diagonalize && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_ORTHO))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: FP64 storage and orthonormal pivoting only");
   if (o->diagonalize && o->block > svd_small_max_block())
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 64");
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 256");
   if (o->panel_pivot && !o->fixed_pivots && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_PERM))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: FP64 storage and the permutation form only");
   FactorPlan P;
@@ -303,7 +304,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Y_doubles = Yd;
   // cooperative launches per block: pivoted QR of the sketch (or the
   // orthonormal form's panel), the panel, and with P-hat one more of each
-  P.nslots = (int)((P.panel_pivot ? 5 : 3) * P.nblocks + 4);
+  P.nslots = (int)((P.panel_pivot ? 5 : 3) * P.nblocks + (P.diag ? P.nblocks : 0) + 4);
   Bump w;
   const size_t d = sizeof(double);
   P.G = w.take((o->G || P.fixed) ? 0 : (size_t)P.ks * m * d);
@@ -335,6 +336,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Z = w.take(P.power > 0 ? (size_t)P.ks * m * d : 0);
   P.Pc = w.take(P.panel_pivot ? (size_t)m * P.b * d : 0);
   P.Rp = w.take(P.panel_pivot ? (size_t)P.b * P.b * d : 0);
+  P.svdw = w.take(P.diag ? svd_small_work_doubles((int)P.b) * d : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -626,6 +628,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   double *W2 = at<double>(work, P.W2);
   double *Z = at<double>(work, P.Z);
   double *Pc = at<double>(work, P.Pc), *Rp = at<double>(work, P.Rp);
+  double *svdw = at<double>(work, P.svdw);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -1033,7 +1036,9 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       {
         ScopedTimer td(h, RQRCP_K_OTHER, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
                        16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi, sd);
-        CHK(launch_svd_small(sd, X, lda, (int)bi, Ud, b, Vd, b), "SVD of the block's triangle");
+        SvdSmall sv{X, lda, (int)bi, Ud, b, Vd, b, svdw, nullptr, nullptr, info, h->limit_ticks};
+        next_slot(&sv.bar, &sv.abort_flag);
+        CHK(launch_svd_small(sd, sv), "SVD of the block's triangle");
         if (ni > bi) {
           GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
           CHK(launch_gemm_f64(sd, gu, vtpart), "U'^T times the block's rows");
@@ -1144,14 +1149,27 @@ static size_t apply_q_work_f64(int64_t m, int64_t k, int64_t b, int64_t ncol) {
   return w.off + 256;
 }
 
+size_t rqrcp_diag_offset(int64_t n, int64_t k, int64_t b) {
+  if (n < 1 || k < 1 || b < 1) return 0;
+  const int64_t nb = cdiv(k, b);
+  size_t vs_total = 0;
+  for (int64_t i = 0; i < nb; ++i) vs_total += (size_t)(n - i * b) * b;
+  return vs_total + (size_t)nb * b + (size_t)nb * b * b;
+}
+
 size_t rqrcp_apply_q_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t k, int64_t b, int64_t ncol) {
   const size_t base = apply_q_work_f64(m, k, b, ncol);
   if (base == 0) return 0;
   return shadow_bytes(dt, (size_t)m * k) + shadow_bytes(dt, (size_t)m * ncol) + base;
 }
 
+// The U'_i of a diagonalised factorization (Section 6.2) act on the rows of
+// block i only, which the reflectors of later blocks do not touch, so
+// Q = H_0 U~_0 H_1 U~_1 ... = (H_0 H_1 ...) (U~_0 U~_1 ...): Q C applies every
+// U'_i to its rows first, Q^T C applies every U'_i^T last.
 static rqrcp_status_t apply_q_impl(rqrcp_handle_t h, int trans, int64_t m, int64_t k, int64_t b, const double *VR,
-                                   int64_t ldvr, const double *T, int64_t ncol, double *C, int64_t ldc, void *work) {
+                                   int64_t ldvr, const double *T, const double *UV, int64_t ncol, double *C,
+                                   int64_t ldc, void *work) {
   hipStream_t s = h->stream;
   Bump w;
   double *Vb = at<double>(work, w.take((size_t)m * b * 8));
@@ -1166,6 +1184,20 @@ static rqrcp_status_t apply_q_impl(rqrcp_handle_t h, int trans, int64_t m, int64
   }
   double *part = at<double>(work, w.take(gp * 8));
   const int64_t nb = cdiv(k, b);
+  auto apply_u = [&]() -> rqrcp_status_t {
+    for (int64_t i = 0; i < nb; ++i) {
+      const int64_t r0 = i * b, bi = std::min(b, k - r0);
+      const double *Ui = UV + (size_t)i * 2 * b * b;
+      GemmF64 gu{trans ? true : false, false, bi, ncol, bi, Ui, b, C + r0, ldc, W1, bi, 1.0, 0.0};
+      CHK(launch_gemm_f64(s, gu, part), trans ? "U'^T C" : "U' C");
+      CHK(launch_copy2d(s, W1, bi, C + r0, ldc, bi, ncol), "rows of the block");
+    }
+    return RQRCP_OK;
+  };
+  if (UV && !trans) {
+    rqrcp_status_t st = apply_u();
+    if (st != RQRCP_OK) return st;
+  }
   for (int64_t t = 0; t < nb; ++t) {
     const int64_t i = trans ? t : nb - 1 - t;
     const int64_t r0 = i * b, bi = std::min(b, k - r0), mi = m - r0;
@@ -1180,12 +1212,13 @@ static rqrcp_status_t apply_q_impl(rqrcp_handle_t h, int trans, int64_t m, int64
     GemmF64 g3{false, false, mi, ncol, bi, Vb, mi, W2, bi, Cs, ldc, -1.0, 1.0};
     CHK(launch_gemm_f64(s, g3, part), "C -= V (T W)");
   }
+  if (UV && trans) return apply_u();
   return RQRCP_OK;
 }
 
 rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t m, int64_t k, int64_t b,
-                             const void *VR, int64_t ldvr, const double *T, int64_t ncol, void *C, int64_t ldc,
-                             void *work, size_t work_bytes) {
+                             const void *VR, int64_t ldvr, const double *T, const double *UV, int64_t ncol,
+                             void *C, int64_t ldc, void *work, size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
@@ -1197,15 +1230,15 @@ rqrcp_status_t rqrcp_apply_q(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
   if (!work || work_bytes < rqrcp_apply_q_work_bytes(dt, m, k, b, ncol))
     return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_q_work_bytes");
   if (dt == RQRCP_F64)
-    return apply_q_impl(h, trans, m, k, b, static_cast<const double *>(VR), ldvr, T, ncol, static_cast<double *>(C),
-                        ldc, work);
+    return apply_q_impl(h, trans, m, k, b, static_cast<const double *>(VR), ldvr, T, UV, ncol,
+                        static_cast<double *>(C), ldc, work);
   hipStream_t s = h->stream;
   Bump w;
   double *V64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * k)));
   double *C64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * ncol)));
   CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, V64, m, m, k), "V to FP64");
   CHK(launch_copy_f32_f64(s, static_cast<const float *>(C), ldc, C64, m, m, ncol), "C to FP64");
-  rqrcp_status_t st = apply_q_impl(h, trans, m, k, b, V64, m, T, ncol, C64, m, at<void>(work, w.off));
+  rqrcp_status_t st = apply_q_impl(h, trans, m, k, b, V64, m, T, UV, ncol, C64, m, at<void>(work, w.off));
   if (st != RQRCP_OK) return st;
   CHK(launch_copy_f64_f32(s, C64, m, static_cast<float *>(C), ldc, m, ncol), "C to FP32");
   return RQRCP_OK;
@@ -1234,8 +1267,13 @@ size_t rqrcp_apply_p_work_bytes(rqrcp_dtype_t dt, int64_t nrow, int64_t n, int64
   return shadow_bytes(dt, (size_t)nrow * n) + base;
 }
 
+// The V'_i of a diagonalised factorization act on the columns of block i
+// only, which the S_j of later blocks do not touch, so
+// P = S_0 V~_0 S_1 V~_1 ... = (S_0 S_1 ...) (V~_0 V~_1 ...): C P applies
+// every V'_i to its columns last, C P^T applies every V'_i^T first.
 static rqrcp_status_t apply_p_impl(rqrcp_handle_t h, int trans, int64_t nrow, int64_t n, int64_t k, int64_t b,
-                                   const int32_t *jpvt, const double *S, double *C, int64_t ldc, void *work) {
+                                   const int32_t *jpvt, const double *S, int diag, double *C, int64_t ldc,
+                                   void *work) {
   hipStream_t s = h->stream;
   Bump w;
   double *tmpc = at<double>(work, w.take((size_t)nrow * n * 8));
@@ -1260,6 +1298,21 @@ static rqrcp_status_t apply_p_impl(rqrcp_handle_t h, int trans, int64_t nrow, in
   size_t vs_total = 0;
   for (int64_t i = 0; i < nb; ++i) { vs_off[i] = vs_total; vs_total += (size_t)(n - i * b) * b; }
   const double *TS = S + vs_total + nb * b;
+  const double *UV = diag ? TS + (size_t)nb * b * b : nullptr;
+  auto apply_v = [&]() -> rqrcp_status_t {
+    for (int64_t i = 0; i < nb; ++i) {
+      const int64_t r0 = i * b, bi = std::min(b, k - r0);
+      const double *Vi = UV + (size_t)i * 2 * b * b + (size_t)b * b;
+      GemmF64 gv{false, trans ? true : false, nrow, bi, bi, C + r0 * ldc, ldc, Vi, b, Z1, nrow, 1.0, 0.0};
+      CHK(launch_gemm_f64(s, gv, part), trans ? "C V'^T" : "C V'");
+      CHK(launch_copy2d(s, Z1, nrow, C + r0 * ldc, ldc, nrow, bi), "columns of the block");
+    }
+    return RQRCP_OK;
+  };
+  if (UV && trans) {
+    rqrcp_status_t st = apply_v();
+    if (st != RQRCP_OK) return st;
+  }
   for (int64_t t = 0; t < nb; ++t) {
     const int64_t i = trans ? nb - 1 - t : t;
     const int64_t r0 = i * b, bi = std::min(b, k - r0), ni = n - r0;
@@ -1273,38 +1326,51 @@ static rqrcp_status_t apply_p_impl(rqrcp_handle_t h, int trans, int64_t nrow, in
     GemmF64 g3{false, true, nrow, ni, bi, Z2, nrow, VS, ni, Cc, ldc, -1.0, 1.0};
     CHK(launch_gemm_f64(s, g3, part), "C -= (..) VS^T");
   }
+  if (UV && !trans) return apply_v();
   return RQRCP_OK;
 }
 
 rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int64_t nrow, int64_t n, int64_t k,
-                             int64_t b, const int32_t *jpvt, const double *S, void *C, int64_t ldc, void *work,
-                             size_t work_bytes) {
+                             int64_t b, const int32_t *jpvt, const double *S, int diagonalized, void *C, int64_t ldc,
+                             void *work, size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (trans != 0 && trans != 1) return fail(h, RQRCP_ERR_ARG, "trans must be 0 or 1");
   if (nrow < 0 || n < 1 || b < 1 || k < 1 || k > n) return fail(h, RQRCP_ERR_ARG, "need nrow >= 0, 1 <= k <= n, b >= 1");
   if (!C || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "C and one of jpvt / S must be given");
+  if (diagonalized != 0 && diagonalized != 1) return fail(h, RQRCP_ERR_ARG, "diagonalized must be 0 or 1");
+  if (diagonalized && !S) return fail(h, RQRCP_ERR_ARG, "diagonalized needs S (orthonormal pivoting)");
   if (ldc < std::max<int64_t>(1, nrow)) return fail(h, RQRCP_ERR_ARG, "ldc must be >= nrow");
   if (nrow == 0) return RQRCP_OK;
   if (!work || work_bytes < rqrcp_apply_p_work_bytes(dt, nrow, n, k, b))
     return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_apply_p_work_bytes");
-  if (dt == RQRCP_F64) return apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, static_cast<double *>(C), ldc, work);
+  if (dt == RQRCP_F64)
+    return apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, diagonalized, static_cast<double *>(C), ldc, work);
   hipStream_t s = h->stream;
   Bump w;
   double *C64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)nrow * n)));
   CHK(launch_copy_f32_f64(s, static_cast<const float *>(C), ldc, C64, nrow, nrow, n), "C to FP64");
-  rqrcp_status_t st = apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, C64, nrow, at<void>(work, w.off));
+  rqrcp_status_t st = apply_p_impl(h, trans, nrow, n, k, b, jpvt, S, diagonalized, C64, nrow, at<void>(work, w.off));
   if (st != RQRCP_OK) return st;
   CHK(launch_copy_f64_f32(s, C64, nrow, static_cast<float *>(C), ldc, nrow, n), "C to FP32");
   return RQRCP_OK;
 }
 
+// Q(:, 0:k) = Q applied to the first k columns of the identity, from a
+// factorization with kf >= k reflector columns.  Reflector j acts on rows
+// >= j, where those columns are zero once j >= k, so only the first k
+// reflectors matter; a diagonalised block's U'_i spreads columns r0..k-1 of
+// the block holding column k - 1 over all its rows, so there that block's
+// reflectors are all needed (blocks past it still act on zero rows only).
+static int64_t qk_columns(int64_t k, int64_t kf, int64_t b, bool diag) {
+  return diag ? std::min(kf, cdiv(k, b) * b) : k;
+}
 static size_t lowrank_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
   if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
   Bump w;
   w.take((size_t)m * k * 8);                               // Q_k
   w.take((size_t)k * n * 8);                               // R_k P^T
-  w.take(std::max(apply_q_work_f64(m, k, b, k), apply_p_work_f64(k, n, n, b)));
+  w.take(std::max(apply_q_work_f64(m, qk_columns(k, n, b, true), b, k), apply_p_work_f64(k, n, n, b)));
   w.take(gemm_part_doubles(m, n, k) * 8);
   return w.off + 256;
 }
@@ -1315,26 +1381,30 @@ size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t 
   return 2 * shadow_bytes(dt, (size_t)m * n) + base;       // VR and A_k in FP64
 }
 
-static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t b, const double *VR, int64_t ldvr,
-                              const double *T, double *Qk, void *work) {
+static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t kf, int64_t b, const double *VR,
+                              int64_t ldvr, const double *T, const double *UV, double *Qk, void *work) {
   CHK(launch_set_identity(h->stream, Qk, m, m, k), "identity");
-  return apply_q_impl(h, 0, m, k, b, VR, ldvr, T, k, Qk, m, work);
+  return apply_q_impl(h, 0, m, qk_columns(k, kf, b, UV != nullptr), b, VR, ldvr, T, UV, k, Qk, m, work);
 }
 
 static rqrcp_status_t lowrank_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t kf, int64_t b,
                                    const double *F, int64_t ldvr, const int32_t *jpvt, const double *T,
-                                   const double *S, double *Ak, int64_t ldak, void *work) {
+                                   const double *S, int diag, double *Ak, int64_t ldak, void *work) {
   hipStream_t s = h->stream;
   Bump w;
   double *Qk = at<double>(work, w.take((size_t)m * k * 8));
   double *RP = at<double>(work, w.take((size_t)k * n * 8));
-  void *sub = at<void>(work, w.take(std::max(apply_q_work_f64(m, k, b, k), apply_p_work_f64(k, n, n, b))));
+  void *sub = at<void>(work, w.take(std::max(apply_q_work_f64(m, qk_columns(k, n, b, true), b, k),
+                                             apply_p_work_f64(k, n, n, b))));
   double *part = at<double>(work, w.take(gemm_part_doubles(m, n, k) * 8));
+  // U'_i, V'_i of a diagonalised factorization: after the V_S blocks, tau_S
+  // and the T_S blocks in S
+  const double *UV = diag ? S + rqrcp_diag_offset(n, kf, b) : nullptr;
   // R_k P^* (k x n)
   CHK(launch_extract_r(s, F, ldvr, k, n, RP, k), "extract R_k");
-  rqrcp_status_t st = apply_p_impl(h, 1, k, n, kf, b, jpvt, S, RP, k, sub);
+  rqrcp_status_t st = apply_p_impl(h, 1, k, n, kf, b, jpvt, S, diag, RP, k, sub);
   if (st != RQRCP_OK) return st;
-  st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
+  st = form_qk(h, m, k, kf, b, F, ldvr, T, UV, Qk, sub);
   if (st != RQRCP_OK) return st;
   GemmF64 g{false, false, m, n, k, Qk, m, RP, k, Ak, ldak, 1.0, 0.0};
   CHK(launch_gemm_f64(s, g, part), "Q_k (R_k P^*)");
@@ -1343,24 +1413,28 @@ static rqrcp_status_t lowrank_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64
 
 rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t kf,
                              int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt, const double *T,
-                             const double *S, void *Ak, int64_t ldak, void *work, size_t work_bytes) {
+                             const double *S, int diagonalized, void *Ak, int64_t ldak, void *work,
+                             size_t work_bytes) {
   if (!h) return fail(nullptr, RQRCP_ERR_ARG, "h is NULL");
   if (dt != RQRCP_F64 && dt != RQRCP_F32) return fail(h, RQRCP_ERR_ARG, "dt: unknown storage type");
   if (m < n || n < 1 || k < 1 || k > n || b < 1) return fail(h, RQRCP_ERR_ARG, "need m >= n >= k >= 1, b >= 1");
   if (kf < k || kf > n) return fail(h, RQRCP_ERR_ARG, "kf (rank of the factorization) must satisfy k <= kf <= n");
   if (!VR || !T || !Ak || (!S && !jpvt)) return fail(h, RQRCP_ERR_ARG, "VR, T, Ak and jpvt (or S) are required");
+  if (diagonalized != 0 && diagonalized != 1) return fail(h, RQRCP_ERR_ARG, "diagonalized must be 0 or 1");
+  if (diagonalized && !S) return fail(h, RQRCP_ERR_ARG, "diagonalized needs S (orthonormal pivoting)");
   if (ldvr < m || ldak < m) return fail(h, RQRCP_ERR_ARG, "ldvr and ldak must be >= m");
   if (!work || work_bytes < rqrcp_lowrank_work_bytes(dt, m, n, k, b))
     return fail(h, RQRCP_ERR_WORKSPACE, "work missing or smaller than rqrcp_lowrank_work_bytes");
   if (dt == RQRCP_F64)
-    return lowrank_impl(h, m, n, k, kf, b, static_cast<const double *>(VR), ldvr, jpvt, T, S,
+    return lowrank_impl(h, m, n, k, kf, b, static_cast<const double *>(VR), ldvr, jpvt, T, S, diagonalized,
                         static_cast<double *>(Ak), ldak, work);
   hipStream_t s = h->stream;
   Bump w;
   double *F64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
   double *Ak64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
   CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, F64, m, m, n), "VR to FP64");
-  rqrcp_status_t st = lowrank_impl(h, m, n, k, kf, b, F64, m, jpvt, T, S, Ak64, m, at<void>(work, w.off));
+  rqrcp_status_t st =
+      lowrank_impl(h, m, n, k, kf, b, F64, m, jpvt, T, S, diagonalized, Ak64, m, at<void>(work, w.off));
   if (st != RQRCP_OK) return st;
   CHK(launch_copy_f64_f32(s, Ak64, m, static_cast<float *>(Ak), ldak, m, n), "A_k to FP32");
   return RQRCP_OK;
@@ -1418,7 +1492,7 @@ static rqrcp_status_t backward_impl(rqrcp_handle_t h, int64_t m, int64_t n, int6
   gp = std::max(gp, gemm_part_doubles(m, n, k));
   double *part = at<double>(work, w.take(gp * 8));
 
-  rqrcp_status_t st = form_qk(h, m, k, b, F, ldvr, T, Qk, sub);
+  rqrcp_status_t st = form_qk(h, m, k, k, b, F, ldvr, T, nullptr, Qk, sub);
   if (st != RQRCP_OK) return st;
   CHK(launch_extract_r(s, F, ldvr, k, n, Rk, k), "extract R_k");
   // P R_k^T (n x k): row jpvt[j] is column j of R_k

@@ -284,9 +284,22 @@ hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S
 
 // SVD of the nb x nb upper triangle of F (ld ldf, nb <= svd_small_max_block()):
 // R22 = U' D V'^T with D decreasing, written as U (nb x nb, ld ldu), V (ld ldv)
-// and D on the diagonal of F, whose strict upper triangle is cleared.
+// and D on the diagonal of F, whose strict upper triangle is cleared.  Above
+// 64 columns a cooperative launch works on the columns in `work`
+// (svd_small_work_doubles) with a zeroed barrier slot (its words from
+// kBarrierWords on count rotations per sweep).
+struct SvdSmall {
+  double *F; int64_t ldf; int nb;
+  double *U; int64_t ldu;
+  double *V; int64_t ldv;
+  double *work;          // svd_small_work_doubles(nb) doubles
+  unsigned *bar;         // zeroed barrier slot (nb > 64)
+  int *abort_flag;
+  int32_t *info;         // may be NULL; [2] is set if a grid-wide wait gave up
+  uint64_t limit_ticks;
+};
 int svd_small_max_block();
-hipError_t launch_svd_small(hipStream_t s, double *F, int64_t ldf, int nb, double *U, int64_t ldu, double *V,
-                            int64_t ldv);
+size_t svd_small_work_doubles(int nb);
+hipError_t launch_svd_small(hipStream_t s, const SvdSmall &p);
 
 }  // namespace rq

@@ -81,7 +81,7 @@ def test_factor_sizes_follow_the_block_structure(lib):
     (100, 100, {"power": 9}, ERR_ARG),                      # q > 8
     (100, 100, {"pivot": "ortho", "panel_pivot": True}, ERR_UNSUPPORTED),  # P-hat: permutation form only
     (100, 100, {"diagonalize": True}, ERR_UNSUPPORTED),     # Section 6.2 blocks: orthonormal pivoting only
-    (100, 100, {"pivot": "ortho", "diagonalize": True, "block": 65}, ERR_UNSUPPORTED),   # b <= 64
+    (400, 400, {"pivot": "ortho", "diagonalize": True, "block": 257}, ERR_UNSUPPORTED),  # b <= 256
 ])
 def test_factor_sizes_rejects_invalid_arguments(lib, m, n, kw, status):
     o = R.make_opts(**kw)
@@ -106,6 +106,10 @@ def test_power_iteration_and_panel_pivoting_need_fp64_storage(lib):
     _, _, s0, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32)
     _, _, s1, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32, diagonalize=True)
     assert s1 - s0 == 2 * 13 * 32 * 32
+    # the U'/V' blocks are the last 2 nb b^2 doubles of S
+    assert lib.rqrcp_diag_offset(400, 400, 32) == s1 - 2 * 13 * 32 * 32 == s0
+    _, _, s2, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=100, rank=250, diagonalize=True)
+    assert lib.rqrcp_diag_offset(400, 250, 100) == s2 - 2 * 3 * 100 * 100
     # fixed pivots draw no sketch: the power setting is ignored
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1, fixed_pivots=True)), *args) == 0
 
