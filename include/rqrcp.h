@@ -99,15 +99,16 @@ typedef struct {
                         /* which rqrcp_check reads                                     */
   int32_t power;        /* q in [0, 8]: steps of the power iteration of Section 6.3 on */
                         /* every sketched block, Y_i = G_i X_i (X_i^T X_i)^q; q > 0    */
-                        /* needs FP64 storage (else RQRCP_ERR_UNSUPPORTED), turns the  */
-                        /* overlapped schedule off and takes (b+p) m more doubles of   */
-                        /* workspace; ignored with fixed_pivots                        */
+                        /* turns the overlapped schedule off and takes (b+p) m more    */
+                        /* doubles of workspace; with F32 storage the steps run on     */
+                        /* FP32 matrix cores (the sketch scaled by a power of two      */
+                        /* before each step); ignored with fixed_pivots                */
   int32_t panel_pivot;  /* 1: Fig. 3's in-block pivot P-hat, a QR with column pivoting */
                         /* of every sketched panel (its order read off a QRCP of the   */
                         /* panel's R', the Remark of Section 2); the columns above the */
-                        /* panel and jpvt follow.  FP64 storage and the permutation    */
-                        /* form only (else RQRCP_ERR_UNSUPPORTED); ignored with        */
-                        /* fixed_pivots.  0 (default): P-hat = I                       */
+                        /* panel and jpvt follow.  The permutation form only (else     */
+                        /* RQRCP_ERR_UNSUPPORTED); ignored with fixed_pivots.          */
+                        /* 0 (default): P-hat = I                                      */
   int32_t diagonalize;  /* 1: diagonalised blocks of Section 6.2 (with ORTHO pivoting   */
                         /* and power: blockRRQR, Fig. 5): each block's b_i x b_i       */
                         /* triangle R22 = U' D V'^T becomes D (decreasing, >= 0), its  */

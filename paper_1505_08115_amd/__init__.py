@@ -258,8 +258,8 @@ def factor(A, block=128, oversample=10, seed=0, pivot="perm", precision="plain",
 
     jpvt: optional int32[n] of fixed pivots (factor A(:, jpvt) without any
     sketch; permutation form only).  power: q steps of the power iteration
-    of Section 6.3 on every sketch (FP64 storage).  panel_pivot: Fig. 3's
-    in-block pivot P-hat (FP64 storage, permutation form).  diagonalize:
+    of Section 6.3 on every sketch.  panel_pivot: Fig. 3's in-block pivot
+    P-hat (permutation form).  diagonalize:
     Section 6.2's diagonal blocks (with pivot="ortho": blockRRQR)."""
     m, n = A.shape
     F = colmajor(A)

@@ -161,6 +161,7 @@ struct FactorPlan {
   size_t Z = 0;        // Y X^T of the power iteration
   size_t Pc = 0, Rp = 0;   // saved panel and its R' (in-block pivoting)
   size_t svdw = 0;         // working columns of the SVD of blocks above 64 columns
+  size_t scal = 0;         // one word for the power-of-two scaling of FP32 power steps
 };
 
 bool block_is_classical_tail(const FactorPlan &P, int64_t i) {
@@ -188,16 +189,14 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->fixed_pivots && o->pivot == RQRCP_PIVOT_ORTHO)
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.fixed_pivots applies to the permutation form only");
   if (o->power < 0 || o->power > 8) return fail(h, RQRCP_ERR_ARG, "opts.power must be in [0, 8]");
-  if (o->power > 0 && dt != RQRCP_F64 && !o->fixed_pivots)
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.power: FP64 storage only");
   if (o->panel_pivot != 0 && o->panel_pivot != 1) return fail(h, RQRCP_ERR_ARG, "opts.panel_pivot must be 0 or 1");
   if (o->diagonalize != 0 && o->diagonalize != 1) return fail(h, RQRCP_ERR_ARG, "opts.diagonalize must be 0 or 1");
   if (o->diagonalize && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_ORTHO))
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: FP64 storage and orthonormal pivoting only");
   if (o->diagonalize && o->block > svd_small_max_block())
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 256");
-  if (o->panel_pivot && !o->fixed_pivots && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_PERM))
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: FP64 storage and the permutation form only");
+  if (o->panel_pivot && !o->fixed_pivots && o->pivot != RQRCP_PIVOT_PERM)
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.panel_pivot: the permutation form only");
   FactorPlan P;
   P.f32 = dt == RQRCP_F32;
   P.mixed = o->precision == RQRCP_PREC_MIXED;
@@ -242,7 +241,11 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
         Yd = std::max(Yd, (size_t)(P.ks * ni));
         const int64_t yrows = P.ortho ? bi : P.ks;
         gpart = std::max(gpart, gemm_part_doubles(yrows, ni, mi));
-        if (P.power > 0) gpart = std::max(gpart, gemm_part_doubles(yrows, mi, ni));
+        if (P.power > 0) {
+          gpart = std::max(gpart, gemm_part_doubles(yrows, mi, ni));
+          gpart32 = std::max(gpart32, gemm_part_floats(yrows, mi, ni));
+          gpart32 = std::max(gpart32, gemm_part_floats(yrows, ni, mi));
+        }
         if (P.f32 && P.mixed) spart = std::max(spart, sample_bf16_part_floats(yrows, ni, mi));
         if (P.f32 && !P.mixed) gpart32 = std::max(gpart32, gemm_part_doubles(yrows, ni, mi));
         if (P.ortho) {
@@ -334,9 +337,10 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.vtpart = w.take(vtp * d);
   P.W2 = w.take(P.f32 ? 0 : (size_t)P.b * n * d);
   P.Z = w.take(P.power > 0 ? (size_t)P.ks * m * d : 0);
-  P.Pc = w.take(P.panel_pivot ? (size_t)m * P.b * d : 0);
+  P.Pc = w.take(P.panel_pivot && !P.f32 ? (size_t)m * P.b * d : 0);
   P.Rp = w.take(P.panel_pivot ? (size_t)P.b * P.b * d : 0);
   P.svdw = w.take(P.diag ? svd_small_work_doubles((int)P.b) * d : 0);
+  P.scal = w.take(P.f32 && P.power > 0 ? 256 : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
     P.V32 = w.take((size_t)m * P.b * 4);
@@ -348,7 +352,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     P.Gb = w.take(sampled && P.mixed ? (size_t)P.ks * m * 2 : 0);
     P.spart = w.take(spart * 4);
     P.G32 = w.take(sampled && !P.mixed ? (size_t)P.ks * m * 4 : 0);
-    P.Y32 = w.take(sampled && !P.mixed ? (size_t)P.ks * n * 4 : 0);
+    P.Y32 = w.take(sampled && (!P.mixed || P.power > 0) ? (size_t)P.ks * n * 4 : 0);
     P.VS32 = w.take(P.ortho ? (size_t)n * P.b * 4 : 0);
     P.TS32 = w.take(P.ortho ? (size_t)P.b * P.b * 4 : 0);
     P.gpart32_aux = w.take(gpaux32 * 4);
@@ -629,6 +633,8 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   double *Z = at<double>(work, P.Z);
   double *Pc = at<double>(work, P.Pc), *Rp = at<double>(work, P.Rp);
   double *svdw = at<double>(work, P.svdw);
+  float *Z32 = at<float>(work, P.Z);   // FP32 storage: Y X^T of the power iteration
+  unsigned *scal = at<unsigned>(work, P.scal);
   int32_t *info = o->info;
   hipStream_t aux = P.pipe ? h->aux : nullptr;
 
@@ -760,6 +766,22 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
               GemmF64 gy{false, false, yrows, ni, mi, Z, ks, X, lda, Y, ks, 1.0, 0.0};
               CHK(launch_gemm_f64(s, gy, gpart), "power iteration (Y X^T) X");
             }
+          } else if (P.power > 0) {
+            // FP32 storage: the steps on FP32 matrix cores from an FP32 copy of
+            // the sketch, which is scaled by a power of two before each step
+            // (its entries grow like |X|^2q, beyond FP32's range for large q;
+            // a scalar factor changes no pivot and no S_i)
+            CHK(launch_copy_f64_f32(s, Y, ks, Y32, ks, yrows, ni), "sketch to FP32");
+            for (int q = 0; q < P.power; ++q) {
+              ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
+                             8.0 * mi * ni + 8.0 * yrows * (mi + ni));
+              CHK(launch_normalise_pow2(s, Y32, ks, yrows, ni, scal), "scale the sketch");
+              GemmF32 gz{false, true, yrows, mi, ni, Y32, ks, X, lda, Z32, ks, 1.f, 0.f};
+              CHK(launch_gemm<float>(s, gz, gpart32), "power iteration Y X^T");
+              GemmF32 gy{false, false, yrows, ni, mi, Z32, ks, X, lda, Y32, ks, 1.f, 0.f};
+              CHK(launch_gemm<float>(s, gy, gpart32), "power iteration (Y X^T) X");
+            }
+            CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
           }
         }
         y_ready = false;
@@ -855,32 +877,40 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
         CHK(launch_gemm_f64(aux, gy, gpart_aux), "sketch product of the next block");
       }
     }
-    // Fig. 3's in-block pivot P-hat (FP64 permutation form): a QR with column
+    // Fig. 3's in-block pivot P-hat (permutation form): a QR with column
     // pivoting of the panel.  Its pivot order depends on the columns only
     // through their Gram matrix, which the triangular factor R' of an
     // unpivoted QR of the panel shares (the Remark of Section 2), so the
     // order is read off a QRCP of the b_i x b_i R'; the saved panel is then
     // restored, its columns (all m rows) and jpvt permuted, and the pivoted
     // panel factored below like any other.
-    if constexpr (!F32) if (P.panel_pivot && !block_is_classical_tail(P, i)) {
+    if (P.panel_pivot && !block_is_classical_tail(P, i)) {
       {
         ScopedTimer tp(h, RQRCP_K_PANEL, 2.0 * mi * bi * bi - 2.0 * bi * bi * bi / 3.0, 40.0 * mi * bi);
-        CHK(launch_copy2d(s, X, lda, Pc, mi, mi, bi), "save the panel");
+        // FP64 storage factors a saved copy's original in place and restores
+        // it; FP32 storage factors an FP64 copy and leaves the panel alone
         PanelQR pq{};
-        pq.P = X; pq.ldp = lda; pq.mi = mi; pq.nb = (int)bi;
+        if constexpr (F32) {
+          CHK(launch_copy_f32_f64(s, X, lda, Pw, mi, mi, bi), "panel to FP64");
+          pq.P = Pw; pq.ldp = mi;
+        } else {
+          CHK(launch_copy2d(s, X, lda, Pc, mi, mi, bi), "save the panel");
+          pq.P = X; pq.ldp = lda;
+        }
+        pq.mi = mi; pq.nb = (int)bi;
         pq.tau = tau + r0; pq.V = Vb; pq.ldv = mi;
         pq.VT = nullptr; pq.ldvt = b;
         pq.part = ppart; pq.red = pred; pq.info = info; pq.block_index = (int)i; pq.limit_ticks = h->limit_ticks;
         next_slot(&pq.bar, &pq.abort_flag);
         CHK(launch_panel_qr(s, pq), "unpivoted QR of the panel");
-        CHK(launch_extract_r(s, X, lda, bi, bi, Rp, bi), "R' of the panel");
+        CHK(launch_extract_r(s, pq.P, pq.ldp, bi, bi, Rp, bi), "R' of the panel");
       }
       {
         ScopedTimer tq(h, RQRCP_K_QRCP, qrcp_flops((double)bi, (double)bi, (double)bi), 8.0 * bi * bi);
         CHK(run_qrcp(Rp, bi, bi, bi, bi, i), "pivoted QR of R'");
       }
       ScopedTimer tm(h, RQRCP_K_MOVES, 0.0, 16.0 * mi * bi + 32.0 * bi * m);
-      CHK(launch_copy2d(s, Pc, mi, X, lda, mi, bi), "restore the panel");
+      if constexpr (!F32) CHK(launch_copy2d(s, Pc, mi, X, lda, mi, bi), "restore the panel");
       CHK(launch_apply_moves<T>(s, A, lda, m, r0, moved, mcnt, dest, (int)(2 * bi), tmp, jpvt, jtmp),
           "move the panel's columns");
     }

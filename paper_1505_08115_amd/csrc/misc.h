@@ -20,6 +20,10 @@ hipError_t launch_scatter_rows_t(hipStream_t s, const double *src, int64_t lds, 
 hipError_t launch_set_identity(hipStream_t s, double *E, int64_t lde, int64_t rows, int64_t cols);
 hipError_t launch_iota(hipStream_t s, int32_t *p, int64_t n);
 hipError_t launch_tri_inv_upper(hipStream_t s, const double *R, int64_t ldr, int64_t k, double *Ri, int64_t ldi);
+// y <- 2^-e y (rows x cols, ld ldy) with e the exponent of max |y|, so that
+// repeated products stay within FP32's range; word: one 32-bit device word of
+// scratch.  The scaling is exact and changes no pivot decision.
+hipError_t launch_normalise_pow2(hipStream_t s, float *y, int64_t ldy, int64_t rows, int64_t cols, unsigned *word);
 hipError_t launch_copy_f32_f64(hipStream_t s, const float *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
                                int64_t cols);
 hipError_t launch_copy_f64_f32(hipStream_t s, const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows,

@@ -151,6 +151,30 @@ __global__ void scatter_cols_t_kernel(const T *__restrict__ s, int64_t lds, int6
   }
 }
 
+// Largest |y| of a column-major block, as the bits of a non-negative float
+// (which order like the values), combined over workgroups with atomicMax on
+// *out (zeroed beforehand).  NaNs are passed over (fmaxf keeps the number).
+__global__ void absmax_bits_kernel(const float *__restrict__ y, int64_t ldy, int64_t rows, int64_t cols,
+                                   unsigned *__restrict__ out) {
+  float mx = 0.f;
+  GRID_STRIDE(i, rows * cols) mx = fmaxf(mx, fabsf(y[i % rows + (i / rows) * ldy]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(mx));
+}
+
+// y <- 2^-e y with e the exponent of the largest |y| (an exact scaling, so
+// that the block's largest entry lies in [1, 2)); nothing for a zero or
+// non-finite maximum.
+__global__ void scale_pow2_kernel(float *__restrict__ y, int64_t ldy, int64_t rows, int64_t cols,
+                                  const unsigned *__restrict__ maxbits) {
+  const float mx = __uint_as_float(*maxbits);
+  if (!(mx > 0.f) || !isfinite(mx)) return;
+  int e = ilogbf(mx);
+  e = e > 120 ? 120 : (e < -120 ? -120 : e);
+  const float sc = ldexpf(1.f, -e);
+  GRID_STRIDE(i, rows * cols) y[i % rows + (i / rows) * ldy] *= sc;
+}
+
 }  // namespace
 
 #define LAUNCH1D(kern, n, ...)                                                         \
@@ -217,6 +241,19 @@ hipError_t launch_tri_inv_upper(hipStream_t s, const double *R, int64_t ldr, int
   const size_t lds = (size_t)k * sizeof(double);
   if (lds > 64 * 1024) return hipErrorInvalidValue;   // at most 8192 columns
   hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((unsigned)k), dim3(kTriThreads), (unsigned)lds, s, R, ldr, k, Ri, ldi);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise_pow2(hipStream_t s, float *y, int64_t ldy, int64_t rows, int64_t cols, unsigned *word) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipError_t e = launch_zero_u32(s, word, 1);
+  if (e != hipSuccess) return e;
+  const int64_t n = rows * cols;
+  hipLaunchKernelGGL(absmax_bits_kernel, dim3(grid_for(n) < 1024 ? grid_for(n) : 1024), dim3(256), 0, s, y, ldy,
+                     rows, cols, word);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scale_pow2_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, ldy, rows, cols, word);
   return hipGetLastError();
 }
 

@@ -92,14 +92,18 @@ def test_factor_sizes_rejects_invalid_arguments(lib, m, n, kw, status):
     assert lib.rqrcp_last_error(None)
 
 
-def test_power_iteration_and_panel_pivoting_need_fp64_storage(lib):
+def test_option_combinations_and_their_workspace(lib):
     a, b, c, d = (ctypes.c_size_t() for _ in range(4))
     args = (ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d))
-    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1)), *args) == ERR_UNSUPPORTED
-    assert lib.rqrcp_factor_sizes(0, 500, 400, ctypes.byref(R.make_opts(power=2)), *args) == 0
-    # P-hat needs FP64 storage as well
-    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == ERR_UNSUPPORTED
-    assert lib.rqrcp_factor_sizes(0, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == 0
+    # the power iteration and P-hat in both storage types, the mixed mode included
+    for dt in (0, 1):
+        assert lib.rqrcp_factor_sizes(dt, 500, 400, ctypes.byref(R.make_opts(power=2)), *args) == 0
+        assert lib.rqrcp_factor_sizes(dt, 500, 400, ctypes.byref(R.make_opts(panel_pivot=True)), *args) == 0
+    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(power=1, precision="mixed")), *args) == 0
+    # power steps hold Y X^T: (b + p) m doubles, within the workspace of every storage type
+    for dt in (torch.float64, torch.float32):
+        _, _, _, w1 = R.factor_sizes(500, 400, dt, power=1)
+        assert w1 >= (128 + 10) * 500 * 8
     # diagonalised blocks: FP64, and S grows by U'_i, V'_i (b x b each) per block
     o = R.make_opts(pivot="ortho", diagonalize=True, block=32)
     assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(o), *args) == ERR_UNSUPPORTED

@@ -386,6 +386,74 @@ def test_fp32_ortho_and_truncated():
         assert float(res) <= 1e-5, f"{pivot}: residual {float(res):.3e}"
 
 
+def _p_from_s(Fz, n, b):
+    """P of an orthonormal-form factorization from its stored S blocks,
+    assembled in FP64 by the definition P = prod_i diag(I, S_i)."""
+    S = Fz.S.cpu().numpy()
+    nb = -(-Fz.rank // b)
+    offs, off = [], 0
+    for i in range(nb):
+        offs.append(off)
+        off += (n - i * b) * b
+    TS0 = off + nb * b
+    P = np.eye(n)
+    for i in range(nb):
+        r0, bi = i * b, min(b, Fz.rank - i * b)
+        VS = S[offs[i]: offs[i] + (n - r0) * b].reshape(b, n - r0).T[:, :bi]
+        TS = S[TS0 + i * b * b: TS0 + (i + 1) * b * b].reshape(b, b).T[:bi, :bi]
+        Pc = P[:, r0:]
+        Pc -= ((Pc @ VS) @ TS) @ VS.T
+    return P
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+@pytest.mark.parametrize("pivot,q,phat", [("perm", 1, False), ("perm", 2, False), ("ortho", 1, False),
+                                           ("perm", 0, True), ("perm", 1, True)])
+def test_fp32_power_iteration_and_panel_pivot(precision, pivot, q, phat):
+    """FP32 storage with the power iteration of Section 6.3 (its steps on
+    FP32 matrix cores, the sketch scaled by a power of two before each) and
+    with Fig. 3's in-block pivot P-hat: the error bounds of every FP32-storage
+    result against the FP32-rounded input (residual <= 1e-5, orthogonality
+    <= 1e-4), |R_ii| within gamma <= 10 sqrt(n) of the singular values (the
+    stated tracking bound) over the singular values above 1e3 u_32 sigma_1,
+    with P-hat every block ordered by decreasing |R_jj|; pivot agreement
+    with the FP64 oracle (same sketches, FP32-rounded input) is reported."""
+    m, n, b, p = 600, 500, 64, 8
+    progress(f"fp32 {precision} {pivot} q={q} P-hat={phat}")
+    s = W.sigma_geometric(n, 6.0)
+    A32 = W.make_matrix(m, n, s, seed=41).numpy().astype(np.float32)
+    info = torch.zeros(4, dtype=torch.int32, device=DEV)
+    Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=p, seed=7, precision=precision, pivot=pivot,
+                  power=q, panel_pivot=phat, info=info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 0, 0, 0]
+    if pivot == "perm":
+        res, orth = _f32_checks(A32, Fz)
+    else:
+        A = A32.astype(np.float64)
+        F = Fz.F.double()
+        Q = torch.linalg.householder_product(F.contiguous(), Fz.tau.contiguous()).cpu().numpy()
+        P = _p_from_s(Fz, n, b)
+        res = np.linalg.norm(A @ P - Q @ np.triu(F.cpu().numpy())[:n]) / np.linalg.norm(A)
+        orth = np.linalg.norm(Q.T @ Q - np.eye(n))
+        assert res <= 1e-5 and orth <= 1e-4, (res, orth)
+    d = np.abs(np.diag(Fz.F.double().cpu().numpy()))
+    keep = s >= 1e3 * 2.0 ** -24 * s[0]
+    gamma = float(np.max(np.maximum(d[keep] / s[keep], s[keep] / d[keep])))
+    assert gamma <= 10 * np.sqrt(n), f"gamma {gamma:.2f}"
+    if phat:
+        for r0 in range(0, n, b):
+            blk = d[r0:r0 + b]
+            assert np.all(blk[:-1] >= blk[1:] * (1 - 1e-12)), f"block at {r0}"
+    ref = O.rqrcp(A32.astype(np.float64), b, p, seed=7, pivot=pivot, power=q, panel_pivot=phat)
+    if pivot == "perm":
+        agree = first_mismatch(Fz.jpvt.cpu().numpy(), ref["jpvt"])
+        agree = f"pivots agree up to {agree if agree >= 0 else n}"
+    else:
+        agree = f"oracle gamma {np.max(np.maximum(np.abs(np.diag(ref['F']))[keep] / s[keep], s[keep] / np.abs(np.diag(ref['F']))[keep])):.2f}"
+    progress(f"  residual {res:.2e} orth {orth:.2e} gamma {gamma:.2f} {agree}")
+
+
 def _widened(Fz):
     """The same factorization with its storage widened to FP64."""
     return R.Factorization(R.colmajor(Fz.F.double()), Fz.jpvt, Fz.tau, Fz.T, Fz.S, Fz.block, Fz.rank, Fz.pivot)
