@@ -158,7 +158,8 @@ def bwd_fwd_ratio(reps=5, dtype=None):
     tb = timed(bwd)
     tr = timed(bwd_recompute)
     agree = float(torch.linalg.norm(state["dA2"] - state["dA"]) / torch.linalg.norm(state["dA"]))
-    name = "FP64" if dtype == torch.float64 else "FP32 storage (FP32 factorization, FP64 truncation/backward)"
+    name = "FP64" if dtype == torch.float64 else ("FP32 storage (FP32 factorization; truncation and backward on FP32 matrix "
+                                                 "cores, their small factors Q_k, R_k, R_11^-1 in FP64)")
     return {"workload": f"C5: {w.m}x{w.n} {name}, b={w.b}, p={w.p}, k={k}", "fwd_ms": tf, "bwd_ms": tb,
             "bwd_recompute_ms": tr, "ratio": tb / tf, "ratio_recompute": tr / tf,
             "recompute_vs_kept_rel_diff": agree, "dtype": "f64" if dtype == torch.float64 else "f32"}

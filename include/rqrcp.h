@@ -246,8 +246,10 @@ rqrcp_status_t rqrcp_apply_p(rqrcp_handle_t h, rqrcp_dtype_t dt, int trans, int6
  * blocks of T and S exist (P is the product of all kf/b S blocks);
  * diagonalized = 1 reads U' and V' from S as rqrcp_apply_q and
  * rqrcp_apply_p describe.  Ak (out)
- * m x n, ld ldak >= m, type dt (F32: VR is widened to FP64, the products run
- * in FP64 and A_k is rounded to FP32).  work: at least rqrcp_lowrank_work_bytes. */
+ * m x n, ld ldak >= m, type dt (F32: Q_k and R_k P^* are formed in FP64 from
+ * widened copies of the reflector columns and of rows 0:k, rounded to FP32,
+ * and their m x n x k product runs on FP32 matrix cores).  work: at least
+ * rqrcp_lowrank_work_bytes. */
 size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);
 rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k,
                              int64_t kf, int64_t b, const void *VR, int64_t ldvr, const int32_t *jpvt,
@@ -263,7 +265,9 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
  * Permutation form only.  A (in) the ORIGINAL input, ld lda.  VR, ldvr, jpvt,
  * T: a factorization of A with rank >= k (e.g. recomputed with fixed_pivots).
  * dAk (in) m x n, ld ldg; dA (out) m x n, ld ldda.  All of type dt (F32:
- * widened to FP64 in the workspace, computed in FP64, dA rounded to FP32).
+ * Q_k, R_k and R_11^{-1} in FP64 from widened copies of the reflector columns
+ * and rows 0:k, rounded to FP32; the products with A, dAk and dA run on FP32
+ * matrix cores on the caller's FP32 data).
  * k <= 8192 (RQRCP_ERR_UNSUPPORTED beyond).
  * work: at least rqrcp_lowrank_backward_work_bytes bytes. */
 size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b);

@@ -1405,10 +1405,24 @@ static size_t lowrank_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
   return w.off + 256;
 }
 
+// FP32 storage: the reflector columns and the rows of R_k widened to FP64,
+// Q_k and R_k P^* formed in FP64 as above, then rounded to FP32 for the
+// m x n x k product on FP32 matrix cores, which writes A_k directly.
+static size_t lowrank_work_f32(int64_t m, int64_t n, int64_t k, int64_t b) {
+  if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
+  const int64_t kq = qk_columns(k, n, b, true);
+  Bump w;
+  w.take((size_t)m * kq * 8);                              // F(:, 0:kq) in FP64
+  w.take((size_t)k * n * 8);                               // F(0:k, :) in FP64
+  w.take((size_t)m * k * 4);                               // Q_k in FP32
+  w.take((size_t)k * n * 4);                               // R_k P^* in FP32
+  w.take(gemm_part_floats(m, n, k) * 4);
+  w.take(lowrank_work_f64(m, n, k, b));
+  return w.off + 256;
+}
+
 size_t rqrcp_lowrank_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
-  const size_t base = lowrank_work_f64(m, n, k, b);
-  if (base == 0) return 0;
-  return 2 * shadow_bytes(dt, (size_t)m * n) + base;       // VR and A_k in FP64
+  return dt == RQRCP_F32 ? lowrank_work_f32(m, n, k, b) : lowrank_work_f64(m, n, k, b);
 }
 
 static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t kf, int64_t b, const double *VR,
@@ -1417,27 +1431,63 @@ static rqrcp_status_t form_qk(rqrcp_handle_t h, int64_t m, int64_t k, int64_t kf
   return apply_q_impl(h, 0, m, qk_columns(k, kf, b, UV != nullptr), b, VR, ldvr, T, UV, k, Qk, m, work);
 }
 
+// Q_k (m x k) and R_k P^* (k x n) in FP64 from a factorization whose
+// reflectors (first columns) are read at Fv, ld ldv, and whose rows 0:k of R
+// at Fr, ld ldr; A_k = Q_k (R_k P^*) follows.
+static rqrcp_status_t lowrank_factors(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t kf, int64_t b,
+                                      const double *Fv, int64_t ldv, const double *Fr, int64_t ldr,
+                                      const int32_t *jpvt, const double *T, const double *S, int diag, double *Qk,
+                                      double *RP, void *sub) {
+  // U'_i, V'_i of a diagonalised factorization: after the V_S blocks, tau_S
+  // and the T_S blocks in S
+  const double *UV = diag ? S + rqrcp_diag_offset(n, kf, b) : nullptr;
+  CHK(launch_extract_r(h->stream, Fr, ldr, k, n, RP, k), "extract R_k");
+  rqrcp_status_t st = apply_p_impl(h, 1, k, n, kf, b, jpvt, S, diag, RP, k, sub);
+  if (st != RQRCP_OK) return st;
+  return form_qk(h, m, k, kf, b, Fv, ldv, T, UV, Qk, sub);
+}
+
 static rqrcp_status_t lowrank_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t kf, int64_t b,
                                    const double *F, int64_t ldvr, const int32_t *jpvt, const double *T,
                                    const double *S, int diag, double *Ak, int64_t ldak, void *work) {
-  hipStream_t s = h->stream;
   Bump w;
   double *Qk = at<double>(work, w.take((size_t)m * k * 8));
   double *RP = at<double>(work, w.take((size_t)k * n * 8));
   void *sub = at<void>(work, w.take(std::max(apply_q_work_f64(m, qk_columns(k, n, b, true), b, k),
                                              apply_p_work_f64(k, n, n, b))));
   double *part = at<double>(work, w.take(gemm_part_doubles(m, n, k) * 8));
-  // U'_i, V'_i of a diagonalised factorization: after the V_S blocks, tau_S
-  // and the T_S blocks in S
-  const double *UV = diag ? S + rqrcp_diag_offset(n, kf, b) : nullptr;
-  // R_k P^* (k x n)
-  CHK(launch_extract_r(s, F, ldvr, k, n, RP, k), "extract R_k");
-  rqrcp_status_t st = apply_p_impl(h, 1, k, n, kf, b, jpvt, S, diag, RP, k, sub);
-  if (st != RQRCP_OK) return st;
-  st = form_qk(h, m, k, kf, b, F, ldvr, T, UV, Qk, sub);
+  rqrcp_status_t st = lowrank_factors(h, m, n, k, kf, b, F, ldvr, F, ldvr, jpvt, T, S, diag, Qk, RP, sub);
   if (st != RQRCP_OK) return st;
   GemmF64 g{false, false, m, n, k, Qk, m, RP, k, Ak, ldak, 1.0, 0.0};
-  CHK(launch_gemm_f64(s, g, part), "Q_k (R_k P^*)");
+  CHK(launch_gemm_f64(h->stream, g, part), "Q_k (R_k P^*)");
+  return RQRCP_OK;
+}
+
+static rqrcp_status_t lowrank_f32(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t kf, int64_t b,
+                                  const float *F, int64_t ldvr, const int32_t *jpvt, const double *T,
+                                  const double *S, int diag, float *Ak, int64_t ldak, void *work) {
+  hipStream_t s = h->stream;
+  const int64_t kq = qk_columns(k, kf, b, diag != 0);
+  Bump w;
+  double *Fv = at<double>(work, w.take((size_t)m * qk_columns(k, n, b, true) * 8));
+  double *Fr = at<double>(work, w.take((size_t)k * n * 8));
+  float *Qk32 = at<float>(work, w.take((size_t)m * k * 4));
+  float *RP32 = at<float>(work, w.take((size_t)k * n * 4));
+  float *part32 = at<float>(work, w.take(gemm_part_floats(m, n, k) * 4));
+  void *rest = at<void>(work, w.off);
+  Bump w2;
+  double *Qk = at<double>(rest, w2.take((size_t)m * k * 8));
+  double *RP = at<double>(rest, w2.take((size_t)k * n * 8));
+  void *sub = at<void>(rest, w2.take(std::max(apply_q_work_f64(m, qk_columns(k, n, b, true), b, k),
+                                              apply_p_work_f64(k, n, n, b))));
+  CHK(launch_copy_f32_f64(s, F, ldvr, Fv, m, m, kq), "reflector columns to FP64");
+  CHK(launch_copy_f32_f64(s, F, ldvr, Fr, k, k, n), "rows of R_k to FP64");
+  rqrcp_status_t st = lowrank_factors(h, m, n, k, kf, b, Fv, m, Fr, k, jpvt, T, S, diag, Qk, RP, sub);
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, Qk, m, Qk32, m, m, k), "Q_k to FP32");
+  CHK(launch_copy_f64_f32(s, RP, k, RP32, k, k, n), "R_k P^* to FP32");
+  GemmF32 g{false, false, m, n, k, Qk32, m, RP32, k, Ak, ldak, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g, part32), "Q_k (R_k P^*) in FP32");
   return RQRCP_OK;
 }
 
@@ -1458,16 +1508,8 @@ rqrcp_status_t rqrcp_lowrank(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int6
   if (dt == RQRCP_F64)
     return lowrank_impl(h, m, n, k, kf, b, static_cast<const double *>(VR), ldvr, jpvt, T, S, diagonalized,
                         static_cast<double *>(Ak), ldak, work);
-  hipStream_t s = h->stream;
-  Bump w;
-  double *F64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  double *Ak64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, F64, m, m, n), "VR to FP64");
-  rqrcp_status_t st =
-      lowrank_impl(h, m, n, k, kf, b, F64, m, jpvt, T, S, diagonalized, Ak64, m, at<void>(work, w.off));
-  if (st != RQRCP_OK) return st;
-  CHK(launch_copy_f64_f32(s, Ak64, m, static_cast<float *>(Ak), ldak, m, n), "A_k to FP32");
-  return RQRCP_OK;
+  return lowrank_f32(h, m, n, k, kf, b, static_cast<const float *>(VR), ldvr, jpvt, T, S, diagonalized,
+                     static_cast<float *>(Ak), ldak, work);
 }
 
 static size_t backward_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
@@ -1493,10 +1535,39 @@ static size_t backward_work_f64(int64_t m, int64_t n, int64_t k, int64_t b) {
   return w.off + 256;
 }
 
+// FP32 storage: Q_k (FP64 from the widened reflector columns), R_k and
+// R_11^{-1} in FP64, rounded to FP32; the products with the m x n operands
+// (A, dA_k, dA) run on FP32 matrix cores straight on the caller's FP32 data.
+static size_t backward_work_f32(int64_t m, int64_t n, int64_t k, int64_t b) {
+  if (m < 1 || n < 1 || k < 1 || b < 1) return 0;
+  Bump w;
+  w.take((size_t)m * k * 8);   // F(:, 0:k) in FP64
+  w.take((size_t)k * n * 8);   // F(0:k, :) in FP64
+  w.take((size_t)m * k * 8);   // Q_k
+  w.take((size_t)k * n * 8);   // R_k
+  w.take((size_t)n * k * 8);   // P R_k^T
+  w.take((size_t)k * k * 8);   // R_11^{-1}
+  w.take(apply_q_work_f64(m, k, b, k));
+  w.take((size_t)m * k * 4);   // Q_k in FP32
+  w.take((size_t)n * k * 4);   // P R_k^T, then dA_k^T Q_k, in FP32
+  w.take((size_t)m * k * 4);   // M
+  w.take((size_t)k * k * 4);   // Q_k^T M
+  w.take((size_t)k * k * 4);   // R_11^{-1} in FP32
+  w.take((size_t)m * k * 4);   // Z
+  w.take((size_t)k * n * 4);   // Q_k^T dA_k
+  size_t gp = 0;
+  gp = std::max(gp, gemm_part_floats(m, k, n));
+  gp = std::max(gp, gemm_part_floats(n, k, m));
+  gp = std::max(gp, gemm_part_floats(k, k, m));
+  gp = std::max(gp, gemm_part_floats(m, k, k));
+  gp = std::max(gp, gemm_part_floats(k, n, m));
+  gp = std::max(gp, gemm_part_floats(m, n, k));
+  w.take(gp * 4);
+  return w.off + 256;
+}
+
 size_t rqrcp_lowrank_backward_work_bytes(rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b) {
-  const size_t base = backward_work_f64(m, n, k, b);
-  if (base == 0) return 0;
-  return 4 * shadow_bytes(dt, (size_t)m * n) + base;       // A, VR, dA_k and dA in FP64
+  return dt == RQRCP_F32 ? backward_work_f32(m, n, k, b) : backward_work_f64(m, n, k, b);
 }
 
 static rqrcp_status_t backward_impl(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t b, const double *A,
@@ -1553,6 +1624,65 @@ static rqrcp_status_t backward_impl(rqrcp_handle_t h, int64_t m, int64_t n, int6
   return RQRCP_OK;
 }
 
+// The same sequence as backward_impl with FP32 operands (see backward_work_f32).
+static rqrcp_status_t backward_f32(rqrcp_handle_t h, int64_t m, int64_t n, int64_t k, int64_t b, const float *A,
+                                   int64_t lda, const float *F, int64_t ldvr, const int32_t *jpvt, const double *T,
+                                   const float *Gb, int64_t ldg, float *dA, int64_t ldda, void *work) {
+  hipStream_t s = h->stream;
+  Bump w;
+  double *Fv = at<double>(work, w.take((size_t)m * k * 8));
+  double *Fr = at<double>(work, w.take((size_t)k * n * 8));
+  double *Qk = at<double>(work, w.take((size_t)m * k * 8));
+  double *Rk = at<double>(work, w.take((size_t)k * n * 8));
+  double *NK = at<double>(work, w.take((size_t)n * k * 8));
+  double *Ri = at<double>(work, w.take((size_t)k * k * 8));
+  void *sub = at<void>(work, w.take(apply_q_work_f64(m, k, b, k)));
+  float *Qk32 = at<float>(work, w.take((size_t)m * k * 4));
+  float *NK32 = at<float>(work, w.take((size_t)n * k * 4));
+  float *M = at<float>(work, w.take((size_t)m * k * 4));
+  float *KK = at<float>(work, w.take((size_t)k * k * 4));
+  float *Ri32 = at<float>(work, w.take((size_t)k * k * 4));
+  float *Z = at<float>(work, w.take((size_t)m * k * 4));
+  float *KN = at<float>(work, w.take((size_t)k * n * 4));
+  size_t gp = 0;
+  gp = std::max(gp, gemm_part_floats(m, k, n));
+  gp = std::max(gp, gemm_part_floats(n, k, m));
+  gp = std::max(gp, gemm_part_floats(k, k, m));
+  gp = std::max(gp, gemm_part_floats(m, k, k));
+  gp = std::max(gp, gemm_part_floats(k, n, m));
+  gp = std::max(gp, gemm_part_floats(m, n, k));
+  float *part = at<float>(work, w.take(gp * 4));
+
+  CHK(launch_copy_f32_f64(s, F, ldvr, Fv, m, m, k), "reflector columns to FP64");
+  CHK(launch_copy_f32_f64(s, F, ldvr, Fr, k, k, n), "rows of R_k to FP64");
+  rqrcp_status_t st = form_qk(h, m, k, k, b, Fv, m, T, nullptr, Qk, sub);
+  if (st != RQRCP_OK) return st;
+  CHK(launch_copy_f64_f32(s, Qk, m, Qk32, m, m, k), "Q_k to FP32");
+  CHK(launch_extract_r(s, Fr, k, k, n, Rk, k), "extract R_k");
+  CHK(launch_scatter_rows_t(s, Rk, k, k, jpvt, n, NK, n), "P R_k^T");
+  CHK(launch_copy_f64_f32(s, NK, n, NK32, n, n, k), "P R_k^T to FP32");
+  GemmF32 g1{false, false, m, k, n, Gb, ldg, NK32, n, M, m, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g1, part), "Gbar P R_k^T");
+  GemmF32 g2{true, false, n, k, m, Gb, ldg, Qk32, m, NK32, n, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g2, part), "Gbar^T Q_k");
+  GemmF32 g3{false, false, m, k, n, A, lda, NK32, n, M, m, 1.f, 1.f};
+  CHK(launch_gemm<float>(s, g3, part), "A (Gbar^T Q_k)");
+  GemmF32 g4{true, false, k, k, m, Qk32, m, M, m, KK, k, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g4, part), "Q_k^T M");
+  GemmF32 g5{false, false, m, k, k, Qk32, m, KK, k, M, m, -1.f, 1.f};
+  CHK(launch_gemm<float>(s, g5, part), "M -= Q_k (Q_k^T M)");
+  CHK(launch_tri_inv_upper(s, Rk, k, k, Ri, k), "R_11^{-1}");
+  CHK(launch_copy_f64_f32(s, Ri, k, Ri32, k, k, k), "R_11^{-1} to FP32");
+  GemmF32 g6{false, true, m, k, k, M, m, Ri32, k, Z, m, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g6, part), "M R_11^{-T}");
+  GemmF32 g7{true, false, k, n, m, Qk32, m, Gb, ldg, KN, k, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g7, part), "Q_k^T Gbar");
+  GemmF32 g8{false, false, m, n, k, Qk32, m, KN, k, dA, ldda, 1.f, 0.f};
+  CHK(launch_gemm<float>(s, g8, part), "Q_k (Q_k^T Gbar)");
+  CHK(launch_scatter_cols_f32(s, Z, m, m, jpvt, k, dA, ldda, n, true), "scatter Z");
+  return RQRCP_OK;
+}
+
 rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t n, int64_t k, int64_t b,
                                       const void *Av, int64_t lda, const void *VR, int64_t ldvr, const int32_t *jpvt,
                                       const double *T, const void *dAkv, int64_t ldg, void *dAv, int64_t ldda,
@@ -1568,19 +1698,8 @@ rqrcp_status_t rqrcp_lowrank_backward(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_
   if (dt == RQRCP_F64)
     return backward_impl(h, m, n, k, b, static_cast<const double *>(Av), lda, static_cast<const double *>(VR), ldvr,
                          jpvt, T, static_cast<const double *>(dAkv), ldg, static_cast<double *>(dAv), ldda, work);
-  hipStream_t s = h->stream;
-  Bump w;
-  double *A64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  double *F64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  double *G64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  double *D64 = at<double>(work, w.take(shadow_bytes(dt, (size_t)m * n)));
-  CHK(launch_copy_f32_f64(s, static_cast<const float *>(Av), lda, A64, m, m, n), "A to FP64");
-  CHK(launch_copy_f32_f64(s, static_cast<const float *>(VR), ldvr, F64, m, m, n), "VR to FP64");
-  CHK(launch_copy_f32_f64(s, static_cast<const float *>(dAkv), ldg, G64, m, m, n), "dA_k to FP64");
-  rqrcp_status_t st = backward_impl(h, m, n, k, b, A64, m, F64, m, jpvt, T, G64, m, D64, m, at<void>(work, w.off));
-  if (st != RQRCP_OK) return st;
-  CHK(launch_copy_f64_f32(s, D64, m, static_cast<float *>(dAv), ldda, m, n), "dA to FP32");
-  return RQRCP_OK;
+  return backward_f32(h, m, n, k, b, static_cast<const float *>(Av), lda, static_cast<const float *>(VR), ldvr,
+                      jpvt, T, static_cast<const float *>(dAkv), ldg, static_cast<float *>(dAv), ldda, work);
 }
 
 }  // extern "C"
