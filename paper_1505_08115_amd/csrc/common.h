@@ -230,6 +230,18 @@ inline hipError_t launch_gemm_f64(hipStream_t s, const GemmF64 &g, double *parti
 // Zero-fill of n 32-bit words (safe inside graph capture, unlike memset nodes).
 hipError_t launch_zero_u32(hipStream_t s, void *p, size_t nwords);
 
+// Launch of a kernel that meets at grid barriers (all its workgroups must be
+// resident at once).  A cooperative launch guarantees that but runs on a
+// hardware queue of its own, and each change of queue between dependent
+// kernels of one stream measured about 12 us (four per block of the
+// factorization).  So the kernel is launched as an ordinary kernel on the
+// stream's own queue when its grid fits in half the device at the kernel's
+// occupancy: the products that run beside it on other streams are capped at
+// the other half (their workgroup cap), so every workgroup finds room.
+// Larger grids take the cooperative launch.
+hipError_t launch_persistent(const void *func, unsigned nwg, unsigned threads, void **args, size_t lds,
+                             hipStream_t s);
+
 // Cooperative pivoted QR of a small k x ncols matrix, first nsteps steps
 // (classical pivot rule; only the pivot decisions are produced).
 struct QrcpSmall {

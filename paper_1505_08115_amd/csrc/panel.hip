@@ -717,8 +717,7 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
   PanelQR pp = p;
   GridBarrier gb{p.bar, p.abort_flag, p.limit_ticks};
   void *args[] = {&pp, &rpw, &gb};
-  return hipLaunchCooperativeKernel((const void *)panel_qr_kernel, dim3(nwg), dim3(kPThreads), args,
-                                    (unsigned)lds, s);
+  return launch_persistent((const void *)panel_qr_kernel, (unsigned)nwg, kPThreads, args, lds, s);
 }
 
 hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S, double *T, int64_t ldt) {

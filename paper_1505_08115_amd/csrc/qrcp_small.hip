@@ -538,7 +538,7 @@ static hipError_t launch_reg(hipStream_t s, int nwg, const QrcpSmall &q) {
   QrcpSmall qq = q;
   GridBarrier gb{q.bar, q.abort_flag, q.limit_ticks};
   void *args[] = {&qq, &gb};
-  return hipLaunchCooperativeKernel((const void *)qrcp_reg_kernel<RPL>, dim3(nwg), dim3(kQThreads), args, 0, s);
+  return launch_persistent((const void *)qrcp_reg_kernel<RPL>, (unsigned)nwg, kQThreads, args, 0, s);
 }
 
 hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
@@ -569,8 +569,7 @@ hipError_t launch_qrcp_small(hipStream_t s, const QrcpSmall &q) {
   QrcpSmall qq = q;
   GridBarrier gb{q.bar, q.abort_flag, q.limit_ticks};
   void *args[] = {&qq, &cpw, &gb};
-  return hipLaunchCooperativeKernel((const void *)qrcp_small_kernel, dim3(nwg), dim3(kQThreads), args,
-                                    (unsigned)lds, s);
+  return launch_persistent((const void *)qrcp_small_kernel, (unsigned)nwg, kQThreads, args, lds, s);
 }
 
 template <typename T>

@@ -67,6 +67,18 @@ __global__ void zero_u32_kernel(uint32_t *p, size_t n) {
 }
 }  // namespace
 
+hipError_t launch_persistent(const void *func, unsigned nwg, unsigned threads, void **args, size_t lds,
+                             hipStream_t s) {
+  int dev = 0, ncu = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, func, (int)threads, lds);
+  if (e != hipSuccess) return e;
+  if ((long)nwg <= (long)occ * (ncu / 2))
+    return hipLaunchKernel(func, dim3(nwg), dim3(threads), args, lds, s);
+  return hipLaunchCooperativeKernel(func, dim3(nwg), dim3(threads), args, (unsigned)lds, s);
+}
+
 hipError_t launch_zero_u32(hipStream_t s, void *p, size_t nwords) {
   if (nwords == 0) return hipSuccess;
   size_t grid = (nwords + 255) / 256;
