@@ -40,6 +40,7 @@ def parse():
                     help="oracle: leading blocks factored on the CPU (0: the whole factorization)")
     ap.add_argument("--no-bwd", action="store_true", help="skip the bwd/fwd ratio measurement (C5)")
     ap.add_argument("--no-c4", action="store_true", help="skip the C4 (16384 x 8192) mixed vs FP64 timing")
+    ap.add_argument("--no-c3", action="store_true", help="skip the C3 (8192^2 orthonormal pivoting) timing")
     ap.add_argument("--power", type=int, default=1,
                     help="also time the workload with this many power-iteration steps (Section 6.3); 0 skips")
     ap.add_argument("--no-panel-pivot", action="store_true",
@@ -105,8 +106,20 @@ def cpu_baseline(A_host, w, nblocks):
     what = (f"the whole {w.name} factorization (the same input, sketches and block size)" if full else
             f"first {nblocks} blocks (rank {k}) of the {w.name} factorization, normalised by the Householder-QR "
             f"flops of those {k} columns")
+    # classical column-pivoted QR (LAPACK dgeqp3 through scipy, threaded BLAS)
+    # as context on the host, at C2's 4096^2 size (it is BLAS-2 bound and
+    # would take minutes at 8192^2); not a parity reference for the
+    # randomized pivots
+    import scipy.linalg
+    Ac = np.array(W.workload_matrix(W.WORKLOADS["C2"]).numpy(), order="F")
+    t1 = time.perf_counter()
+    scipy.linalg.qr(Ac, pivoting=True, mode="r", overwrite_a=True, check_finite=False)
+    dq = time.perf_counter() - t1
+    geqp3 = {"workload": f"classical QRCP (LAPACK dgeqp3 via scipy) of C2's {Ac.shape[0]}x{Ac.shape[1]} FP64 "
+                         f"matrix on the host", "seconds": dq,
+             "value": W.flops_normalised(*Ac.shape) / dq / 1e9, "unit": "GFLOP/s"}
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{what}, {dt:.1f} s wall", "seconds": dt}
+            "sample": f"{what}, {dt:.1f} s wall", "seconds": dt, "context_classical_qrcp": geqp3}
 
 
 def bwd_fwd_ratio(reps=5, dtype=None):
@@ -328,6 +341,21 @@ def main():
                        "breakdown": {k: v[1] / args.steps for k, v in p4p.items()}},
               "speedup_mixed_vs_fp64": p4 / m4}
 
+    # C3: the orthonormal-pivoting form (Section 4.2, eq. Ycols) at 8192^2,
+    # b = 256, p = 10 (its parity and invariants are a GPU test of their own)
+    c3 = None
+    if w.name == "H1" and not args.no_c3:
+        w3 = W.WORKLOADS["C3"]
+        A3 = W.workload_matrix(w3, device=dev)
+        t3, (_, p3), _, i3 = run(w3, A3, min(args.steps, 3), 1, True, check=False)
+        del A3
+        m3 = float(np.mean(t3))
+        c3 = {"workload": f"C3: {w3.m}x{w3.n} FP64, orthonormal pivoting, b={w3.b}, p={w3.p}, sigma 1/j with a "
+                          f"1e-6 gap after 2048",
+              "ms_per_step": m3, "value": W.flops_normalised(w3.m, w3.n) / (m3 * 1e-3) / 1e9, "info": i3,
+              "slowdown_vs_permutation": m3 / ms,
+              "breakdown": {k: v[1] / min(args.steps, 3) for k, v in p3.items()}}
+
     # the same factorization with q steps of the power iteration on every
     # sketch (Section 6.3): two more products per block, serial schedule
     power = None
@@ -413,7 +441,7 @@ def main():
         "roofline_dominant": dominant,
         "extra": {"residual": res, "info": info, "step_ms": times, "breakdown": breakdown, "latency": latency,
                   "update_uncapped": uncapped,
-                  "mixed": mixed, "c4": c4, "power_iteration": power, "panel_pivot": phat},
+                  "mixed": mixed, "c4": c4, "c3": c3, "power_iteration": power, "panel_pivot": phat},
     }
     if not args.no_bwd:
         out["extra"]["methods_123"] = methods_123()
