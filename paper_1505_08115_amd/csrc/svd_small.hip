@@ -392,10 +392,17 @@ __global__ __launch_bounds__(kCoopThreads) void svd_finish_kernel(double *__rest
     if (lane == 0) sig[c] = sqrt(s2);
   }
   __syncthreads();
-  // decreasing singular values; equal values keep their column order
+  // decreasing singular values; equal values keep their column order, and a
+  // non-finite value (from a non-finite input) sorts last, so that the ranks
+  // always form a permutation
   if (t < n) {
+    auto key = [&](int c) { return sig[c] == sig[c] ? sig[c] : -1.0; };
+    const double kt = key(t);
     int rank = 0;
-    for (int o = 0; o < n; ++o) rank += (sig[o] > sig[t]) || (sig[o] == sig[t] && o < t);
+    for (int o = 0; o < n; ++o) {
+      const double ko = key(o);
+      rank += (ko > kt) || (ko == kt && o < t);
+    }
     order[rank] = t;
   }
   __syncthreads();

@@ -276,3 +276,19 @@ def test_method_3_on_C3s_at_block_256(q):
     ratio = np.abs(np.log(d_gpu / w.sigma()))
     progress(f"  median |log(D/sigma)| = {np.median(ratio):.2e}, max {ratio.max():.2e}")
     assert np.median(ratio) <= (0.05 if q == 2 else 0.1)
+
+
+@pytest.mark.parametrize("b", [32, 128])
+def test_diagonalised_blocks_with_a_non_finite_input(b):
+    """A NaN in the input reaches the SVD of the blocks' triangles: the
+    factorization reports it in the info word (non-finite norm met, no
+    grid-wide wait given up), and the finishing kernel's sort of the singular
+    values still forms a permutation (a non-finite value sorts last)."""
+    m, n = 300, 256
+    A = W.make_matrix(m, n, W.sigma_geometric(n, 3.0), seed=3).numpy()
+    A[5, 7] = np.nan
+    progress(f"blockRRQR non-finite input b={b}")
+    Fz = R.factor(torch.tensor(A, device=DEV), block=b, oversample=8, seed=2, pivot="ortho", power=1,
+                  diagonalize=True)
+    iv = Fz.check()
+    assert iv[0] == 1 and iv[1] >= 1 and iv[2] == 0
