@@ -99,8 +99,9 @@ typedef struct {
                         /* which rqrcp_check reads                                     */
   int32_t power;        /* q in [0, 8]: steps of the power iteration of Section 6.3 on */
                         /* every sketched block, Y_i = G_i X_i (X_i^T X_i)^q; q > 0    */
-                        /* turns the overlapped schedule off and takes (b+p) m more    */
-                        /* doubles of workspace; with F32 storage the steps run on     */
+                        /* moves the trailing update to the caller's stream (the steps */
+                        /* read the updated block) and takes (b+p) m more doubles of   */
+                        /* workspace; with F32 storage the steps run on                */
                         /* FP32 matrix cores (the sketch scaled by a power of two      */
                         /* before each step); ignored with fixed_pivots                */
   int32_t panel_pivot;  /* 1: Fig. 3's in-block pivot P-hat, a QR with column pivoting */

@@ -287,7 +287,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (!P.f32) gpart32 = 0;
   // the next block's sketch product and this block's trailing update may run
   // on the auxiliary stream (own split-K room), the correction G V on the main
-  P.pipe = (!P.f32 || P.mixed) && !P.ortho && !P.fixed && P.power == 0;
+  P.pipe = (!P.f32 || P.mixed) && !P.ortho && !P.fixed;
   size_t gpaux = 0, gpaux32 = 0;
   if (P.pipe)
     for (int64_t i = 0; i + 1 < P.nblocks; ++i) {
@@ -755,34 +755,36 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
               CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
             }
           }
-          // Section 6.3: q steps of the power iteration in the row form of the
-          // sample, Y_i := (Y_i X_i^T) X_i, so that Y_i = G_i X_i (X_i^T X_i)^q
-          if constexpr (!F32) {
-            for (int q = 0; q < P.power; ++q) {
-              ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
-                             16.0 * mi * ni + 16.0 * yrows * (mi + ni));
-              GemmF64 gz{false, true, yrows, mi, ni, Y, ks, X, lda, Z, ks, 1.0, 0.0};
-              CHK(launch_gemm_f64(s, gz, gpart), "power iteration Y X^T");
-              GemmF64 gy{false, false, yrows, ni, mi, Z, ks, X, lda, Y, ks, 1.0, 0.0};
-              CHK(launch_gemm_f64(s, gy, gpart), "power iteration (Y X^T) X");
-            }
-          } else if (P.power > 0) {
-            // FP32 storage: the steps on FP32 matrix cores from an FP32 copy of
-            // the sketch, which is scaled by a power of two before each step
-            // (its entries grow like |X|^2q, beyond FP32's range for large q;
-            // a scalar factor changes no pivot and no S_i)
-            CHK(launch_copy_f64_f32(s, Y, ks, Y32, ks, yrows, ni), "sketch to FP32");
-            for (int q = 0; q < P.power; ++q) {
-              ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
-                             8.0 * mi * ni + 8.0 * yrows * (mi + ni));
-              CHK(launch_normalise_pow2(s, Y32, ks, yrows, ni, scal), "scale the sketch");
-              GemmF32 gz{false, true, yrows, mi, ni, Y32, ks, X, lda, Z32, ks, 1.f, 0.f};
-              CHK(launch_gemm<float>(s, gz, gpart32), "power iteration Y X^T");
-              GemmF32 gy{false, false, yrows, ni, mi, Z32, ks, X, lda, Y32, ks, 1.f, 0.f};
-              CHK(launch_gemm<float>(s, gy, gpart32), "power iteration (Y X^T) X");
-            }
-            CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
+        }
+        // Section 6.3: q steps of the power iteration in the row form of the
+        // sample, Y_i := (Y_i X_i^T) X_i, so that Y_i = G_i X_i (X_i^T X_i)^q
+        // (also on a sample that the previous block formed and corrected:
+        // its update ran on this stream, so X_i is the updated block)
+        if constexpr (!F32) {
+          for (int q = 0; q < P.power; ++q) {
+            ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
+                           16.0 * mi * ni + 16.0 * yrows * (mi + ni));
+            GemmF64 gz{false, true, yrows, mi, ni, Y, ks, X, lda, Z, ks, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, gz, gpart), "power iteration Y X^T");
+            GemmF64 gy{false, false, yrows, ni, mi, Z, ks, X, lda, Y, ks, 1.0, 0.0};
+            CHK(launch_gemm_f64(s, gy, gpart), "power iteration (Y X^T) X");
           }
+        } else if (P.power > 0) {
+          // FP32 storage: the steps on FP32 matrix cores from an FP32 copy of
+          // the sketch, which is scaled by a power of two before each step
+          // (its entries grow like |X|^2q, beyond FP32's range for large q;
+          // a scalar factor changes no pivot and no S_i)
+          CHK(launch_copy_f64_f32(s, Y, ks, Y32, ks, yrows, ni), "sketch to FP32");
+          for (int q = 0; q < P.power; ++q) {
+            ScopedTimer tp(h, RQRCP_K_SAMPLE_GEMM, 4.0 * yrows * ni * mi,
+                           8.0 * mi * ni + 8.0 * yrows * (mi + ni));
+            CHK(launch_normalise_pow2(s, Y32, ks, yrows, ni, scal), "scale the sketch");
+            GemmF32 gz{false, true, yrows, mi, ni, Y32, ks, X, lda, Z32, ks, 1.f, 0.f};
+            CHK(launch_gemm<float>(s, gz, gpart32), "power iteration Y X^T");
+            GemmF32 gy{false, false, yrows, ni, mi, Z32, ks, X, lda, Y32, ks, 1.f, 0.f};
+            CHK(launch_gemm<float>(s, gy, gpart32), "power iteration (Y X^T) X");
+          }
+          CHK(launch_copy_f32_f64(s, Y32, ks, Y, ks, yrows, ni), "sketch to FP64");
         }
         y_ready = false;
         if (!P.ortho) {
@@ -998,17 +1000,26 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       if (pipe_next) {
         if constexpr (!F32) {
           // the update on the auxiliary stream, the next sketch's correction here
-          CHK(hipEventRecord(h->ev_vt, s), "update fork event");
-          CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
-          {
+          if (P.power > 0) {
+            // the next block's power steps read the updated block: the update
+            // runs here, on the whole chip
             ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
-                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
             GemmF64 gu{false, false, mi, ni - bi, bi, Vb, mi, W2, bi, C, lda, -1.0, 1.0, true};
-            gu.max_wg = beside_qrcp;
-            CHK(launch_gemm_f64(aux, gu, gpart_aux), "C -= V (T^T W)");
+            CHK(launch_gemm_f64(s, gu, gpart), "C -= V (T^T W)");
+          } else {
+            CHK(hipEventRecord(h->ev_vt, s), "update fork event");
+            CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
+            {
+              ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
+                             (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+              GemmF64 gu{false, false, mi, ni - bi, bi, Vb, mi, W2, bi, C, lda, -1.0, 1.0, true};
+              gu.max_wg = beside_qrcp;
+              CHK(launch_gemm_f64(aux, gu, gpart_aux), "C -= V (T^T W)");
+            }
+            CHK(hipEventRecord(h->ev_upd, aux), "update event");
+            upd_pending = true;
           }
-          CHK(hipEventRecord(h->ev_upd, aux), "update event");
-          upd_pending = true;
           CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product and G V");
           ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * nc, 8.0 * (ks * bi + 2.0 * ks * nc + bi * nc));
           GemmF64 g2{false, false, ks, ni - bi, bi, GVb, ks, W2, bi, Y, ks, -1.0, 1.0};
@@ -1018,17 +1029,24 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           // FP32 storage: the update C -= (V T^T) W on the auxiliary stream;
           // the correction of the next sketch here, in FP64, as
           // ((G V) T^T) W with W widened from FP32
-          CHK(hipEventRecord(h->ev_vt, s), "update fork event");
-          CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
-          {
+          if (P.power > 0) {
             ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
-                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+                           (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc));
             GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
-            gu.max_wg = beside_qrcp;
-            CHK(launch_gemm<float>(aux, gu, gpart32_aux), "C -= (V T^T) W");
+            CHK(launch_gemm<float>(s, gu, gpart32), "C -= (V T^T) W");
+          } else {
+            CHK(hipEventRecord(h->ev_vt, s), "update fork event");
+            CHK(hipStreamWaitEvent(aux, h->ev_vt, 0), "auxiliary stream wait");
+            {
+              ScopedTimer t3(h, RQRCP_K_UPDATE_GEMM, 2.0 * mi * nc * bi,
+                             (double)sizeof(T) * (2.0 * mi * nc + mi * bi + bi * nc), aux);
+              GemmF32 gu{false, false, mi, ni - bi, bi, Vt32, mi, W32, bi, C, lda, -1.f, 1.f, true};
+              gu.max_wg = beside_qrcp;
+              CHK(launch_gemm<float>(aux, gu, gpart32_aux), "C -= (V T^T) W");
+            }
+            CHK(hipEventRecord(h->ev_upd, aux), "update event");
+            upd_pending = true;
           }
-          CHK(hipEventRecord(h->ev_upd, aux), "update event");
-          upd_pending = true;
           CHK(hipStreamWaitEvent(s, h->ev_ypre, 0), "wait for the next sketch product and G V");
           ScopedTimer tc(h, RQRCP_K_SAMPLE_GEMM, 2.0 * ks * bi * nc + 2.0 * ks * bi * bi,
                          8.0 * (ks * bi + 2.0 * ks * nc + bi * nc) + 4.0 * bi * nc);
