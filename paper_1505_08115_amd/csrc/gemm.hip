@@ -215,12 +215,15 @@ __global__ __launch_bounds__(NT, 1) void gemm_kernel_capped(int64_t M, int64_t N
 // 128-column slab of C, so the large operand B is read from HBM exactly once
 // (a tiled kernel with 128-row tiles re-reads it once per row tile).  512
 // threads = 8 waves, wave w owns columns 16w .. 16w+15 of the slab and all
-// MT row blocks of 16; K is split over workgroups to fill the chip.
+// MT row blocks of 16; K is split over workgroups to fill the chip.  With TB
+// the large operand is stored N x K (the power iteration's Y X^T): it is read
+// with the column index fastest, so each row of a K slab is one coalesced
+// 1 KiB segment.
 constexpr int kRowsBN = 128;
 constexpr int kTagTrail = 1, kTagW = 2;   // kernel-name tags (profiles only)
 constexpr int kRowsThreads = 512;
 
-template <typename T, int MT, bool TA, bool SPLIT>
+template <typename T, int MT, bool TA, bool TB, bool SPLIT>
 __device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
                                                int64_t ldb, T *__restrict__ C, int64_t ldc, T alpha, T beta,
@@ -237,16 +240,23 @@ __device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, 
   const int64_t kend = min(K, kbeg + kchunk);
   const bool interior = n0 + kRowsBN <= N;
 
-  // B slab (k fastest): k = t % 16, column j = t / 16 + 32 q
-  const int b_k = t % kBK, b_j = t / kBK;
+  // B slab: k = t % 16, column j = t / 16 + 32 q (k fastest); with TB
+  // column j = t % 128, k = t / 128 + 4 q (column fastest)
+  constexpr int KQ = kRowsThreads / kRowsBN;   // 4 rows of the K slab per pass with TB
+  const int b_k = TB ? t / kRowsBN : t % kBK, b_j = TB ? t % kRowsBN : t / kBK;
   T ra[AE], rb[BE];
   auto load = [&](int64_t k0) {
     const bool fullk = k0 + kBK <= kend;
-    const T *pb = B + (k0 + b_k) + (n0 + b_j) * ldb;
+    const T *pb = TB ? B + (n0 + b_j) + (k0 + b_k) * ldb : B + (k0 + b_k) + (n0 + b_j) * ldb;
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
-      const bool okq = (interior && fullk) || (n0 + b_j + 32 * q < N && k0 + b_k < kend);
-      rb[q] = okq ? pb[(int64_t)32 * q * ldb] : T(0);
+      if constexpr (TB) {
+        const bool okq = (interior && fullk) || (n0 + b_j < N && k0 + b_k + KQ * q < kend);
+        rb[q] = okq ? pb[(int64_t)KQ * q * ldb] : T(0);
+      } else {
+        const bool okq = (interior && fullk) || (n0 + b_j + 32 * q < N && k0 + b_k < kend);
+        rb[q] = okq ? pb[(int64_t)32 * q * ldb] : T(0);
+      }
     }
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
@@ -260,7 +270,10 @@ __device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, 
   };
   auto stash = [&](int st) {
 #pragma unroll
-    for (int q = 0; q < BE; ++q) Bs[st][b_k][b_j + 32 * q] = rb[q];
+    for (int q = 0; q < BE; ++q) {
+      if constexpr (TB) Bs[st][b_k + KQ * q][b_j] = rb[q];
+      else Bs[st][b_k][b_j + 32 * q] = rb[q];
+    }
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
       const int f = t + kRowsThreads * q;
@@ -312,18 +325,18 @@ __device__ __forceinline__ void gemm_rows_slab(int64_t M, int64_t N, int64_t K, 
   }
 }
 
-template <typename T, int MT, bool TA, bool SPLIT, int TAG = 0>
+template <typename T, int MT, bool TA, bool TB, bool SPLIT, int TAG = 0>
 __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                                  const T *__restrict__ A, int64_t lda,
                                                                  const T *__restrict__ B, int64_t ldb,
                                                                  T *__restrict__ C, int64_t ldc, T alpha, T beta,
                                                                  T *__restrict__ partial) {
-  gemm_rows_slab<T, MT, TA, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
-                                   (int64_t)blockIdx.x * kRowsBN);
+  gemm_rows_slab<T, MT, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                       (int64_t)blockIdx.x * kRowsBN);
 }
 
 // A capped grid: slabs blockIdx.x, blockIdx.x + gridDim.x, ... of 128 columns.
-template <typename T, int MT, bool TA, bool SPLIT>
+template <typename T, int MT, bool TA, bool TB, bool SPLIT>
 __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel_capped(int64_t M, int64_t N, int64_t K,
                                                                         int64_t kchunk, const T *__restrict__ A,
                                                                         int64_t lda, const T *__restrict__ B,
@@ -331,7 +344,8 @@ __global__ __launch_bounds__(kRowsThreads) void gemm_rows_kernel_capped(int64_t 
                                                                         T alpha, T beta, T *__restrict__ partial) {
   const int64_t nslab = (N + kRowsBN - 1) / kRowsBN;
   for (int64_t sl = blockIdx.x; sl < nslab; sl += gridDim.x)
-    gemm_rows_slab<T, MT, TA, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial, sl * kRowsBN);
+    gemm_rows_slab<T, MT, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
+                                         sl * kRowsBN);
 }
 
 template <typename T, int TAG = 0>
@@ -423,17 +437,17 @@ void split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   *kchunk = kc;
 }
 
-// The all-rows kernel takes products with 64 < M <= 448 (288 in FP64), A and
-// B untransposed and a long K (the sketch G X, and V^T C with V^T stored
-// explicitly); everything else goes to the tiled kernel.  (A transposed
-// operand would be read as many short strided segments, which measured
-// slower than the tiled kernel.)
+// The all-rows kernel takes products with 64 < M <= 448 (288 in FP64), A
+// untransposed, B either way, and a long K (the sketch G X, V^T C with V^T
+// stored explicitly, the power iteration's Y X^T); everything else goes to
+// the tiled kernel.  (A transposed A would be read as many short strided
+// segments, which measured slower than the tiled kernel.)
 template <typename T>
 constexpr int rows_max_mt() { return sizeof(T) == 8 ? 18 : 28; }   // FP64 accumulators: 8 VGPRs per block
 
 template <typename T>
 bool use_rows(const Gemm<T> &g) {
-  return !g.ta && !g.tb && g.M > 64 && g.M <= 16 * rows_max_mt<T>() && g.K >= 256 && g.N >= 256;
+  return !g.ta && g.M > 64 && g.M <= 16 * rows_max_mt<T>() && g.K >= 256 && g.N >= 256;
 }
 
 // One workgroup per CU (its LDS stages take most of the CU's 160 KiB), so the
@@ -460,33 +474,34 @@ void rows_split_plan(const Gemm<T> &g, int *splits, int64_t *kchunk) {
   *kchunk = kc;
 }
 
-template <typename T, int MT, bool TA, int TAG>
+template <typename T, int MT, bool TA, bool TB, int TAG>
 hipError_t launch_rows_tag(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
   const int64_t slabs = (g.N + kRowsBN - 1) / kRowsBN;
   if (g.max_wg > 0 && slabs * splits > g.max_wg) {
     dim3 cg((unsigned)std::max<int64_t>(1, g.max_wg / splits), (unsigned)splits);
     if (splits > 1)
-      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, true>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, TB, true>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
                          kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
     else
-      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, false>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+      hipLaunchKernelGGL((gemm_rows_kernel_capped<T, MT, TA, TB, false>), cg, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
                          kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
     return hipGetLastError();
   }
   dim3 grid((unsigned)slabs, (unsigned)splits);
   if (splits > 1)
-    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, true, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, TB, true, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
                        kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   else
-    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, false, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
+    hipLaunchKernelGGL((gemm_rows_kernel<T, MT, TA, TB, false, TAG>), grid, dim3(kRowsThreads), 0, s, g.M, g.N, g.K,
                        kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial);
   return hipGetLastError();
 }
 
 template <typename T, int MT, bool TA>
 hipError_t launch_rows_mt(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchunk, T *partial) {
-  if (g.wprod) return launch_rows_tag<T, MT, TA, kTagW>(s, g, splits, kchunk, partial);
-  return launch_rows_tag<T, MT, TA, 0>(s, g, splits, kchunk, partial);
+  if (g.tb) return launch_rows_tag<T, MT, TA, true, 0>(s, g, splits, kchunk, partial);
+  if (g.wprod) return launch_rows_tag<T, MT, TA, false, kTagW>(s, g, splits, kchunk, partial);
+  return launch_rows_tag<T, MT, TA, false, 0>(s, g, splits, kchunk, partial);
 }
 
 template <typename T, bool TA>
