@@ -116,8 +116,10 @@ typedef struct {
                         /* rows right of it get U'^T and its columns above it V'.      */
                         /* Q = prod_i diag(I, (I - V_i T_i V_i^T) diag(U'_i, I)) and   */
                         /* P = prod_i diag(I, S_i) diag(I, V'_i, I); U'_i, V'_i (b x b, */
-                        /* ld b) follow the T_S blocks in S (see rqrcp_factor).  FP64, */
-                        /* ORTHO and b <= 256 only (else RQRCP_ERR_UNSUPPORTED).       */
+                        /* ld b) follow the T_S blocks in S (see rqrcp_factor).  ORTHO */
+                        /* and b <= 256 only (else RQRCP_ERR_UNSUPPORTED); with F32    */
+                        /* storage the SVD and its products run in FP64 on widened     */
+                        /* copies of the block's triangle, rows and columns            */
                         /* rqrcp_apply_q (its UV argument), rqrcp_apply_p and          */
                         /* rqrcp_lowrank (their diagonalized flag) apply U' and V';    */
                         /* rqrcp_lowrank_backward covers the permutation form only     */

@@ -161,6 +161,7 @@ struct FactorPlan {
   size_t Z = 0;        // Y X^T of the power iteration
   size_t Pc = 0, Rp = 0;   // saved panel and its R' (in-block pivoting)
   size_t svdw = 0;         // working columns of the SVD of blocks above 64 columns
+  size_t r22 = 0;          // FP32 storage: the block's triangle widened for its SVD
   size_t scal = 0;         // one word for the power-of-two scaling of FP32 power steps
 };
 
@@ -191,8 +192,8 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   if (o->power < 0 || o->power > 8) return fail(h, RQRCP_ERR_ARG, "opts.power must be in [0, 8]");
   if (o->panel_pivot != 0 && o->panel_pivot != 1) return fail(h, RQRCP_ERR_ARG, "opts.panel_pivot must be 0 or 1");
   if (o->diagonalize != 0 && o->diagonalize != 1) return fail(h, RQRCP_ERR_ARG, "opts.diagonalize must be 0 or 1");
-  if (o->diagonalize && (dt != RQRCP_F64 || o->pivot != RQRCP_PIVOT_ORTHO))
-    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: FP64 storage and orthonormal pivoting only");
+  if (o->diagonalize && o->pivot != RQRCP_PIVOT_ORTHO)
+    return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: orthonormal pivoting only");
   if (o->diagonalize && o->block > svd_small_max_block())
     return fail(h, RQRCP_ERR_UNSUPPORTED, "opts.diagonalize: block at most 256");
   if (o->panel_pivot && !o->fixed_pivots && o->pivot != RQRCP_PIVOT_PERM)
@@ -340,6 +341,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Pc = w.take(P.panel_pivot && !P.f32 ? (size_t)m * P.b * d : 0);
   P.Rp = w.take(P.panel_pivot ? (size_t)P.b * P.b * d : 0);
   P.svdw = w.take(P.diag ? svd_small_work_doubles((int)P.b) * d : 0);
+  P.r22 = w.take(P.diag && P.f32 ? (size_t)P.b * P.b * d : 0);
   P.scal = w.take(P.f32 && P.power > 0 ? 256 : 0);
   if (P.f32) {
     P.Pw = w.take((size_t)m * P.b * d);
@@ -633,6 +635,7 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
   double *Z = at<double>(work, P.Z);
   double *Pc = at<double>(work, P.Pc), *Rp = at<double>(work, P.Rp);
   double *svdw = at<double>(work, P.svdw);
+  double *r22 = at<double>(work, P.r22);
   float *Z32 = at<float>(work, P.Z);   // FP32 storage: Y X^T of the power iteration
   unsigned *scal = at<unsigned>(work, P.scal);
   int32_t *info = o->info;
@@ -1072,11 +1075,11 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     }
     // Section 6.2: R22 = U' D V'^T; U-tilde = Q-tilde diag(U', I) puts U'^T on
     // the block's rows right of it, V' multiplies its columns above it, and
-    // the triangle becomes D (orthonormal pivoting, FP64).  None of it is read
-    // by the next block's sketch, power steps or QR of the sketch (rows and
-    // columns past this block; their own buffers), so it runs on the side
-    // stream (one workgroup for the SVD) beside them
-    if constexpr (!F32) if (P.diag) {
+    // the triangle becomes D (orthonormal pivoting; in FP64, on widened copies
+    // with FP32 storage).  None of it is read by the next block's sketch,
+    // power steps or QR of the sketch (rows and columns past this block; their
+    // own buffers), so it runs on the side stream beside them
+    if (P.diag) {
       double *Ud = UVd + (size_t)i * 2 * b * b, *Vd = Ud + (size_t)b * b;
       hipStream_t sd = h->side;
       CHK(hipEventRecord(h->fork_ev, s), "fork event");
@@ -1084,18 +1087,40 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       {
         ScopedTimer td(h, RQRCP_K_OTHER, 22.0 * bi * bi * bi + 2.0 * bi * bi * (ni - bi + r0),
                        16.0 * bi * (ni - bi + r0) + 24.0 * bi * bi, sd);
-        SvdSmall sv{X, lda, (int)bi, Ud, b, Vd, b, svdw, nullptr, nullptr, info, h->limit_ticks};
-        next_slot(&sv.bar, &sv.abort_flag);
-        CHK(launch_svd_small(sd, sv), "SVD of the block's triangle");
-        if (ni > bi) {
-          GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
-          CHK(launch_gemm_f64(sd, gu, vtpart), "U'^T times the block's rows");
-          CHK(launch_copy2d(sd, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
-        }
-        if (r0 > 0) {
-          GemmF64 gv{false, false, r0, bi, bi, A + r0 * lda, lda, Vd, b, Vt, r0, 1.0, 0.0};
-          CHK(launch_gemm_f64(sd, gv, vtpart), "columns above the block times V'");
-          CHK(launch_copy2d(sd, Vt, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
+        if constexpr (!F32) {
+          SvdSmall sv{X, lda, (int)bi, Ud, b, Vd, b, svdw, nullptr, nullptr, info, h->limit_ticks};
+          next_slot(&sv.bar, &sv.abort_flag);
+          CHK(launch_svd_small(sd, sv), "SVD of the block's triangle");
+          if (ni > bi) {
+            GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, X + bi * lda, lda, Wb, bi, 1.0, 0.0};
+            CHK(launch_gemm_f64(sd, gu, vtpart), "U'^T times the block's rows");
+            CHK(launch_copy2d(sd, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
+          }
+          if (r0 > 0) {
+            GemmF64 gv{false, false, r0, bi, bi, A + r0 * lda, lda, Vd, b, Vt, r0, 1.0, 0.0};
+            CHK(launch_gemm_f64(sd, gv, vtpart), "columns above the block times V'");
+            CHK(launch_copy2d(sd, Vt, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
+          }
+        } else {
+          // the block (its reflectors below the triangle come back unchanged:
+          // FP32 -> FP64 -> FP32 is exact, and the SVD writes only the triangle)
+          CHK(launch_copy_f32_f64(sd, X, lda, r22, b, bi, bi), "triangle to FP64");
+          SvdSmall sv{r22, b, (int)bi, Ud, b, Vd, b, svdw, nullptr, nullptr, info, h->limit_ticks};
+          next_slot(&sv.bar, &sv.abort_flag);
+          CHK(launch_svd_small(sd, sv), "SVD of the block's triangle");
+          CHK(launch_copy_f64_f32(sd, r22, b, X, lda, bi, bi), "triangle to FP32");
+          if (ni > bi) {
+            CHK(launch_copy_f32_f64(sd, X + bi * lda, lda, Vt, bi, bi, ni - bi), "rows of the block to FP64");
+            GemmF64 gu{true, false, bi, ni - bi, bi, Ud, b, Vt, bi, Wb, bi, 1.0, 0.0};
+            CHK(launch_gemm_f64(sd, gu, vtpart), "U'^T times the block's rows");
+            CHK(launch_copy_f64_f32(sd, Wb, bi, X + bi * lda, lda, bi, ni - bi), "rows of the block");
+          }
+          if (r0 > 0) {
+            CHK(launch_copy_f32_f64(sd, A + r0 * lda, lda, Vt, r0, r0, bi), "columns above the block to FP64");
+            GemmF64 gv{false, false, r0, bi, bi, Vt, r0, Vd, b, Wb, r0, 1.0, 0.0};
+            CHK(launch_gemm_f64(sd, gv, vtpart), "columns above the block times V'");
+            CHK(launch_copy_f64_f32(sd, Wb, r0, A + r0 * lda, lda, r0, bi), "columns above the block");
+          }
         }
       }
       CHK(hipEventRecord(h->ev_diag, sd), "diagonalisation event");

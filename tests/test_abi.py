@@ -104,9 +104,10 @@ def test_option_combinations_and_their_workspace(lib):
     for dt in (torch.float64, torch.float32):
         _, _, _, w1 = R.factor_sizes(500, 400, dt, power=1)
         assert w1 >= (128 + 10) * 500 * 8
-    # diagonalised blocks: FP64, and S grows by U'_i, V'_i (b x b each) per block
+    # diagonalised blocks in either storage type; S grows by U'_i, V'_i (b x b each) per block
     o = R.make_opts(pivot="ortho", diagonalize=True, block=32)
-    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(o), *args) == ERR_UNSUPPORTED
+    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(o), *args) == 0
+    assert lib.rqrcp_factor_sizes(1, 500, 400, ctypes.byref(R.make_opts(diagonalize=True)), *args) == ERR_UNSUPPORTED
     _, _, s0, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32)
     _, _, s1, _ = R.factor_sizes(500, 400, torch.float64, pivot="ortho", block=32, diagonalize=True)
     assert s1 - s0 == 2 * 13 * 32 * 32

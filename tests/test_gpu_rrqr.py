@@ -292,3 +292,53 @@ def test_diagonalised_blocks_with_a_non_finite_input(b):
                   diagonalize=True)
     iv = Fz.check()
     assert iv[0] == 1 and iv[1] >= 1 and iv[2] == 0
+
+
+@pytest.mark.parametrize("m,n,b,q,precision", [(300, 256, 64, 1, "plain"), (600, 520, 128, 1, "mixed"),
+                                                (600, 520, 256, 2, "plain")])
+def test_diagonalised_blocks_with_fp32_storage(m, n, b, q, precision):
+    """FP32 storage (plain, or mixed with the BF16 sketch): the triangles'
+    SVD and U'^T, V' products run in FP64 on widened copies.  Against the
+    FP64 oracle on the FP32-rounded input (plain, q = 1): D within 1e-5 |A|
+    (the FP32 rounding of the stored trailing matrices); every case: D on the
+    singular values (median |log(D/sigma)|), exactly diagonal blocks with
+    D >= 0 decreasing, Q^T A P = R within 1e-5, Q (reflectors stored in FP32)
+    orthogonal to 1e-4 and P (FP64 S blocks and V') to the FP64 bar."""
+    A32 = W.make_matrix(m, n, W.sigma_geometric(n, 4.0), seed=m + b).numpy().astype(np.float32)
+    A = A32.astype(np.float64)
+    progress(f"blockRRQR FP32 {precision} m={m} n={n} b={b} q={q}")
+    Fz = R.factor(torch.tensor(A32, device=DEV), block=b, oversample=10, seed=9, pivot="ortho", power=q,
+                  precision=precision, diagonalize=True)
+    assert Fz.check() == [0, 0, 0, 0]
+    nA = np.linalg.norm(A)
+    d = np.diag(Fz.F.double().cpu().numpy())
+    if precision == "plain" and q == 1:
+        # (with q = 2 the FP32 power steps keep a block's weak directions only
+        # to about u_32 (sigma_1 / sigma_b)^5 of the rows' weight, 1e-6 at b = 256
+        # here, so the span a block picks, and its D, legitimately move away
+        # from the FP64 oracle's; there D is held to the singular values below)
+        ref = O.rqrcp(A, b, 10, seed=9, pivot="ortho", power=q, diagonalize=True)
+        progress(f"  max |D - D_oracle| / |A| = {np.max(np.abs(d - np.diag(ref['F']))) / nA:.2e}")
+        assert np.max(np.abs(d - np.diag(ref["F"]))) <= 1e-5 * nA
+    res = _as_result(Fz, m, n, b)
+    res["F"] = Fz.F.double().cpu().numpy()
+    Rg = np.triu(res["F"])
+    for r0, bi in res["blocks"]:
+        blk = Rg[r0:r0 + bi, r0:r0 + bi]
+        dd = np.diag(blk)
+        assert np.all(blk - np.diag(dd) == 0.0)
+        assert np.all(dd >= 0) and np.all(dd[:-1] >= dd[1:])
+    Q, P = O.form_q(res, m), O.form_p(res)
+    resid = np.linalg.norm(Q.T @ A @ P - Rg) / nA
+    progress(f"  |Q^T A P - R| / |A| = {resid:.2e}")
+    assert resid <= 1e-5
+    # Q from reflectors stored in FP32 (with T and U' in FP64): the FP32-storage
+    # bar of every other test; P from the FP64 S blocks and V': the FP64 bar
+    assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 1e-4
+    assert np.linalg.norm(P.T @ P - np.eye(n)) <= _orth_bar(n, b)
+    s_ = np.linalg.svd(A, compute_uv=False)
+    ratio = np.abs(np.log(d / s_))
+    progress(f"  median |log(D/sigma)| = {np.median(ratio):.2e}")
+    # 0.003-0.009 at q = 1; 0.09 at q = 2, where the FP32 power steps blur the
+    # blocks' weak directions (see above)
+    assert np.median(ratio) <= (0.1 if q == 1 else 0.15)
