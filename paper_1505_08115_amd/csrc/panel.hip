@@ -14,7 +14,10 @@
 //     v = (x_j - beta e_j)/(alpha - beta), the reflector's action on column c
 //     follows from the reduced sums alone: v^T x_c = (g_c - beta x_c(j)) /
 //     (alpha - beta).  Degenerate columns follow the conventions of the
-//     oracle: tau = 0 for a zero column or a column of length one.
+//     oracle: tau = 0 for a zero column or a column of length one.  Up to
+//     four columns share one exchange: the reflectors leave inner products
+//     over rows >= j unchanged, so the sums of x_{j+u}^T x_c and the entries
+//     of rows j .. j+3 determine all four reflectors and their action.
 //   * after a slab: the partial products V_s^T [V_s | A_rest] are
 //     reduce-scattered (two barriers); they give the slab's Gram block
 //     V_s^T V_s for its T_s and W = V_s^T A_rest, which updates the rest of
@@ -33,6 +36,11 @@ constexpr int W = kPanelW;
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kPThreads = 256;
 constexpr size_t kLdsDoubles = 20480 - 256;
+constexpr int kG = 4;                       // columns per exchange in a column step
+constexpr int kGW = kG * W;                 // sums (or row entries) per exchange
+constexpr int kNH = kPThreads / kGW;        // workgroup sets in the reduction of the sums
+constexpr int kLd = (64 + kNH - 1) / kNH;   // loads in flight per thread in that reduction
+static_assert(kPThreads % kGW == 0 && 2 * kGW % 64 == 0, "column-step layout");
 
 __device__ void flag_nonfinite(int32_t *info, int block_index) {
   if (!info) return;
@@ -48,15 +56,15 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
   double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
   double *Wp = X + (size_t)W * ldx;         // W x nb    reduced V_s^T [V_s | A_rest], row t at Wp + t*nb (columns >= cs)
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
-  double *sc = Ts + W * W;                  // 640       reduction scratch
-  double *taus = sc + 640;                  // W
+  double *sc = Ts + W * W;                  // 5 kGW     reduction scratch
+  double *taus = sc + 5 * kGW;              // W
 
   const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
   const int64_t rbeg = (int64_t)wg * rpw;
   const int nrow = (int)max((int64_t)0, min((int64_t)rpw, p.mi - rbeg));
   const int nslab = (nb + W - 1) / W;
-  double *part_cs = p.part;                                   // [2][nwg][4W]
-  double *part_up = p.part + (size_t)2 * nwg * 4 * W;         // [nwg][W*nb]
+  double *part_cs = p.part;                                   // [2][nwg][2 kGW]
+  double *part_up = p.part + (size_t)2 * nwg * 2 * kGW;       // [nwg][W*nb]
   unsigned gen = 0;
   bool ok = true;
   int step = 0;
@@ -81,156 +89,222 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       const int64_t j = cs + jj;
       const int E = ws - jj;
       const int buf = step & 1;
-      // Columns jj and jj+1 share one exchange when both lie in the slab and
-      // column jj+1 keeps at least two rows from its diagonal down.  H_j acts
-      // orthogonally on rows >= j, so (H_j x_{j+1})^T (H_j x_c) over those
-      // rows equals x_{j+1}^T x_c: the reflector of column j+1 and its action
-      // follow from the sums over rows >= j of x_j^T x_c and x_{j+1}^T x_c and
-      // the entries of rows j and j+1.
-      const bool pair = jj + 1 < ws && j + 2 < p.mi;
-      // partial sums over own rows >= j: [g0 | h0 | g1 | h1] at sc[0 .. 4W),
-      // g0_c = x_jj^T x_c, g1_c = x_{jj+1}^T x_c, h0_c = x_c(j), h1_c = x_c(j+1)
+      // Up to kG columns jj, jj+1, ... share one exchange; column jj+u joins
+      // only if it lies in the slab and keeps at least two rows from its
+      // diagonal down.  H_j ... H_{j+u-1} act orthogonally on rows >= j, so
+      // inner products of transformed columns over those rows are the sums of
+      // the original columns: every reflector of the group and its action on
+      // the slab follow from the sums over rows >= j of x_{jj+u}^T x_c and the
+      // entries of rows j .. j+kG-1.
+      const int gc = (int)max((int64_t)1, min((int64_t)min(kG, E), p.mi - j - 1));
+      // partial sums over own rows >= j: Gm at sc[u*W + c - jj] (u < kG) and
+      // the row entries h at sc[kGW + s*W + c - jj], Gm_u,c = x_{jj+u}^T x_c,
+      // h_s,c = x_c(j + s)
       {
+        // straight-line passes over 4 rows (the loads first); a column past
+        // the slab or the group reads column W - 1 (its sums are not kept) and
+        // rows past nrow count as zero
         const int c = jj + (t >> 3), sub = t & 7;
-        double g0 = 0.0, g1 = 0.0;
-        if (c < ws) {
-          const int r0 = (int)max((int64_t)0, j - rbeg);
-          if (pair) {
-            for (int r = r0 + sub; r < nrow; r += 8) {
-              const double xc = X[c * ldx + r];
-              g0 += X[jj * ldx + r] * xc;
-              g1 += X[(jj + 1) * ldx + r] * xc;
-            }
-          } else {
-            for (int r = r0 + sub; r < nrow; r += 8) g0 += X[jj * ldx + r] * X[c * ldx + r];
+        const int cx = min(c, W - 1) * ldx;
+        int gx[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) gx[u] = min(jj + u, W - 1) * ldx;
+        double g[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) g[u] = 0.0;
+        for (int r = (int)max((int64_t)0, j - rbeg) + sub; r < nrow; r += 32) {
+          double xc[4], xg[4][kG];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int ri = min(r + 8 * i, nrow - 1);
+            xc[i] = X[cx + ri];
+#pragma unroll
+            for (int u = 0; u < kG; ++u) xg[i][u] = X[gx[u] + ri];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double xi = r + 8 * i < nrow ? xc[i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kG; ++u) g[u] += xg[i][u] * xi;
           }
         }
-        g0 = group8_sum(g0);
-        g1 = group8_sum(g1);
+#pragma unroll
+        for (int u = 0; u < kG; ++u) g[u] = group8_sum(g[u]);
         if (sub == 0 && c < ws) {
-          const double h0 = (j >= rbeg && j < rbeg + nrow) ? X[c * ldx + (int)(j - rbeg)] : 0.0;
-          const double h1 = (j + 1 >= rbeg && j + 1 < rbeg + nrow) ? X[c * ldx + (int)(j + 1 - rbeg)] : 0.0;
-          sc[c - jj] = g0;
-          sc[W + (c - jj)] = h0;
-          sc[2 * W + (c - jj)] = g1;
-          sc[3 * W + (c - jj)] = h1;
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            const int64_t row = j + u;
+            sc[u * W + (c - jj)] = g[u];
+            sc[kGW + u * W + (c - jj)] = (row >= rbeg && row < rbeg + nrow) ? X[cx + (int)(row - rbeg)] : 0.0;
+          }
         }
         __syncthreads();
-        // wave 0 publishes this workgroup's values (two per lane)
+        // wave 0 publishes this workgroup's values
         if (t < 64) {
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
+          for (int q = 0; q < 2 * kGW / 64; ++q) {
             const int e = t + 64 * q;
-            if (e % W < E && (q == 0 || pair)) st_agent(part_cs + ((size_t)buf * nwg + wg) * 4 * W + e, sc[e]);
+            if (e % W < E && (e / W) % kG < gc) st_agent(part_cs + ((size_t)buf * nwg + wg) * 2 * kGW + e, sc[e]);
           }
         }
       }
       // exchange mode: the partials are written and read with agent-scope atomics
       ok = grid_sync(gb, gen, false, true);
       if (!ok) break;
-      // fixed-order reduction of the sums g0, g1: 4 groups of workgroups, then
-      // the groups in order; thread (grp, e) sums entry e of [g0 | g1].  The
-      // row entries h0, h1 are read once, from the workgroups owning rows j
-      // and j + 1 (every other workgroup's are zero).
+      // fixed-order reduction of the sums Gm: kNH sets of workgroups (w mod
+      // kNH), each summed in workgroup order, then the sets in order; thread
+      // (set, e) sums entry e.  The row entries h are read once, from the
+      // workgroups owning rows j .. j + gc - 1 (every other workgroup's are zero).
       {
-        const int e = t & 63, grp = t >> 6;
-        const int ent = e < W ? e : 2 * W + (e - W);             // g0_e or g1_(e-W)
-        const bool live = e < W ? e < E : (pair && e - W < E);
+        const int e = t % kGW, set = t / kGW;
+        const bool live = e % W < E && e / W < gc;
         double acc = 0.0;
-        // 16 loads in flight per thread (one round trip at 64 workgroups), summed in workgroup order
-        for (int w0 = grp; w0 < nwg; w0 += 64) {
-          double x[16];
+        // kLd loads in flight per thread (one round trip at 64 workgroups)
+        for (int w0 = set; w0 < nwg; w0 += kNH * kLd) {
+          double x[kLd];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int w2 = w0 + 4 * u;
-            const double *src = part_cs + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 4 * W;
-            x[u] = (live && w2 < nwg) ? ld_agent(src + ent) : 0.0;
+          for (int u = 0; u < kLd; ++u) {
+            const int w2 = w0 + kNH * u;
+            const double *src = part_cs + ((size_t)buf * nwg + (w2 < nwg ? w2 : 0)) * 2 * kGW;
+            x[u] = (live && w2 < nwg) ? ld_agent(src + e) : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < 16; ++u) acc += x[u];
+          for (int u = 0; u < kLd; ++u) acc += x[u];
         }
-        double h = 0.0;
-        if (grp == 0 && live) {
-          const int64_t row = e < W ? j : j + 1;
-          const int owner = (int)(row / rpw);
-          h = ld_agent(part_cs + ((size_t)buf * nwg + owner) * 4 * W + ent + W);
+        if (set == kNH - 1) {
+          double h = 0.0;
+          if (live) {
+            const int owner = (int)((j + e / W) / rpw);
+            h = ld_agent(part_cs + ((size_t)buf * nwg + owner) * 2 * kGW + kGW + e);
+          }
+          sc[kGW + e] = h;
         }
-        sc[grp * 128 + ent] = acc;
-        sc[grp * 128 + ent + W] = h;
+        sc[2 * kGW + set * kGW + e] = acc;
         __syncthreads();
-        if (t < 128) sc[t] = ((sc[t] + sc[128 + t]) + sc[256 + t]) + sc[384 + t];
+        if (t < kGW) {
+          double s = sc[2 * kGW + t];
+#pragma unroll
+          for (int q = 1; q < kNH; ++q) s += sc[2 * kGW + q * kGW + t];
+          sc[t] = s;
+        }
         __syncthreads();
       }
-      // Every thread forms the reflector(s) from the reduced sums itself (the
-      // same operations on the same LDS values, so all threads agree bit for
-      // bit): no serial section and no barrier before the column factors.
-      const double alpha = sc[W], nrm2 = sc[0];
-      double beta = alpha, tau = 0.0, scale = 1.0;
-      if (j < p.mi - 1) {
-        if (nrm2 != 0.0) {
-          beta = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(nrm2);
-          tau = (beta - alpha) / beta;
-          scale = alpha - beta;
-        } else {
-          beta = 0.0;
+      // Every thread forms the group's reflectors from the reduced sums itself
+      // (the same operations on the same LDS values, so all threads agree bit
+      // for bit): no serial section and no barrier before the column factors.
+      // Column u after H_j ... H_{j+u-1}: its entries on rows j .. j+u-1 are R
+      // entries, and its inner product with a column c over rows >= j+u is
+      // Gm_u,c minus the products of their R entries on those rows.  Each
+      // thread carries the group's columns (zg) and, beside them, column
+      // jj + t (zc), whose factors f_tt = tau_tt v_tt^T (H_{j+tt-1} ... H_j x_c)
+      // go to sc[4 kGW + tt*W + t]; a factor is zero where reflector tt does
+      // not act (tt at or past the group's end, or column jj + t at or before
+      // jj + tt), so the row updates below apply all kG reflectors blindly.
+      double bet[kG], tau[kG], rsv[kG];
+      int ng = 1;
+      {
+        const int tc = min(t, W - 1);
+        double zg[kG][kG], zc[kG], vq[kG], rr[kG];
+#pragma unroll
+        for (int s2 = 0; s2 < kG; ++s2) {
+          zc[s2] = sc[kGW + s2 * W + tc];
+#pragma unroll
+          for (int u = 0; u < kG; ++u) zg[u][s2] = sc[kGW + s2 * W + u];
+        }
+        bool open = true;
+#pragma unroll
+        for (int tt = 0; tt < kG; ++tt) {
+          // reflector tt from column tt after the earlier ones
+          bool act;
+          double scale;
+          if (tt == 0) {
+            const double alpha = zg[0][0], nrm2 = sc[0];
+            bet[0] = alpha;
+            tau[0] = 0.0;
+            scale = 1.0;
+            if (j < p.mi - 1) {
+              if (nrm2 != 0.0) {
+                bet[0] = (alpha >= 0.0 ? -1.0 : 1.0) * sqrt(nrm2);
+                tau[0] = (bet[0] - alpha) / bet[0];
+                scale = alpha - bet[0];
+              } else {
+                bet[0] = 0.0;
+              }
+            }
+            act = true;
+            open = tau[0] != 0.0;
+            if (t == 0 && (!(nrm2 == nrm2) || nrm2 > 1.79e308)) flag_nonfinite(p.info, p.block_index);
+          } else {
+            // column tt joins while its norm over rows >= j+tt, Gm_tt,tt minus
+            // the squares of its R entries, keeps more than half of Gm_tt,tt
+            // (relative error below 2 u); otherwise it takes a step of its own
+            const double guu = sc[tt * W + tt];
+            double nrm = guu;
+#pragma unroll
+            for (int s2 = 0; s2 < tt; ++s2) nrm -= zg[tt][s2] * zg[tt][s2];
+            act = open && tt < gc && guu > 0.0 && guu < 1.79e308 && nrm > 0.5 * guu;
+            open = act;
+            const double y = zg[tt][tt];
+            const double b = (y >= 0.0 ? -1.0 : 1.0) * sqrt(act ? nrm : 1.0);
+            bet[tt] = act ? b : 0.0;
+            tau[tt] = act ? (b - y) / b : 0.0;
+            scale = act ? y - b : 1.0;
+            if (act) ng = tt + 1;
+          }
+          // v = (x - beta e_j) / scale is formed as a product with 1/scale (one
+          // division per thread instead of one per use)
+          rsv[tt] = 1.0 / scale;
+#pragma unroll
+          for (int s2 = 0; s2 < kG; ++s2) {
+            rr[s2] = s2 < tt ? zg[tt][s2] : 0.0;
+            vq[s2] = s2 > tt ? zg[tt][s2] * rsv[tt] : 0.0;
+          }
+          // reflector tt on the later group columns and on column jj + t
+#pragma unroll
+          for (int u = tt + 1; u < kG; ++u) {
+            double ip = sc[tt * W + u];
+#pragma unroll
+            for (int s2 = 0; s2 < tt; ++s2) ip -= rr[s2] * zg[u][s2];
+            double f = tau[tt] * ((ip - bet[tt] * zg[u][tt]) * rsv[tt]);
+            f = act ? f : 0.0;
+            zg[u][tt] -= f;
+#pragma unroll
+            for (int s2 = tt + 1; s2 < kG; ++s2) zg[u][s2] -= f * vq[s2];
+          }
+          {
+            double ip = sc[tt * W + tc];
+#pragma unroll
+            for (int s2 = 0; s2 < tt; ++s2) ip -= rr[s2] * zc[s2];
+            double f = tau[tt] * ((ip - bet[tt] * zc[tt]) * rsv[tt]);
+            f = act && t > tt ? f : 0.0;
+            if (t < W) sc[4 * kGW + tt * W + t] = f;
+            zc[tt] -= f;
+#pragma unroll
+            for (int s2 = tt + 1; s2 < kG; ++s2) zc[s2] -= f * vq[s2];
+          }
         }
       }
-      // v = (x - beta e_j) / scale is formed as a product with 1/scale (one
-      // division per thread instead of one per use)
-      const double rs = 1.0 / scale;
-      // column jj+1 after H_j: y = H_j x_{j+1}; its norm over rows > j is
-      // g1_{jj+1} - y(j)^2, taken only while the subtracted part is less
-      // than half (relative error below 2 u); otherwise a step of its own
-      int two = 0;
-      double beta1 = 0.0, tau1 = 0.0, scale1 = 1.0, v0n = 0.0, yj = 0.0;
-      if (pair && tau != 0.0) {
-        const double f01 = tau * ((sc[1] - beta * sc[W + 1]) * rs);
-        yj = sc[W + 1] - f01;
-        v0n = sc[3 * W] * rs;                         // v_j(j+1)
-        const double y1 = sc[3 * W + 1] - f01 * v0n;  // y(j+1)
-        const double g11 = sc[2 * W + 1];
-        const double n1 = g11 - yj * yj;
-        if (g11 > 0.0 && g11 < 1.79e308 && n1 > 0.5 * g11) {
-          two = 1;
-          beta1 = (y1 >= 0.0 ? -1.0 : 1.0) * sqrt(n1);
-          tau1 = (beta1 - y1) / beta1;
-          scale1 = y1 - beta1;
-        }
-      }
-      const double rs1 = 1.0 / scale1;
       if (t == 0) {
-        if (!(nrm2 == nrm2) || nrm2 > 1.79e308) flag_nonfinite(p.info, p.block_index);
-        taus[jj] = tau;
-        if (two) taus[jj + 1] = tau1;
-        if (wg == 0) {
-          p.tau[j] = tau;
-          if (two) p.tau[j + 1] = tau1;
-        }
-      }
-      // f0_c = tau v_j^T x_c at sc[512 + c - jj]; with a pair, f1_c =
-      // tau1 v_{j+1}^T (H_j x_c) at sc[576 + c - jj] for c > jj + 1
-      if (t > 0 && t < E) {
-        const double f0 = tau * ((sc[t] - beta * sc[W + t]) * rs);
-        sc[512 + t] = f0;
-        if (two && t > 1) {
-          const double zj = sc[W + t] - f0, zj1 = sc[3 * W + t] - f0 * v0n;
-          const double yz = sc[2 * W + t] - yj * zj;   // y^T z over rows > j
-          sc[576 + t] = tau1 * ((yz - beta1 * zj1) * rs1);
-        }
+#pragma unroll
+        for (int u = 0; u < kG; ++u)
+          if (u < ng) {
+            taus[jj + u] = tau[u];
+            if (wg == 0) p.tau[j + u] = tau[u];
+          }
       }
       // Row updates: G threads per row (G = 1 when a workgroup has more than
       // 128 rows; then a thread takes rows t and t + 256, rpw being below
       // 512), thread (r, g) takes the columns c = jj + 1 + g, jj + 1 + g + G,
-      // ...  The reflector columns' entries of the row are read before the
-      // barrier: group 0 overwrites them with the scaled reflector after it.
+      // ...  The group columns' entries of the row are read before the
+      // barrier: their owners overwrite them with R entries and reflectors.
       const int G = max(1, min(kPThreads / max(nrow, 1), 8));
       const int nitem = nrow * G;
-      double xr0[2], xr1[2];
+      double xg[2][kG];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int idx = t + q * kPThreads, r = idx % max(nrow, 1);
-        xr0[q] = idx < nitem ? X[jj * ldx + r] : 0.0;
-        xr1[q] = idx < nitem && two ? X[(jj + 1) * ldx + r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kG; ++u) xg[q][u] = X[min(jj + u, W - 1) * ldx + r];
       }
       __syncthreads();
 #pragma unroll
@@ -240,58 +314,57 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         const int r = idx % nrow, ug = idx / nrow;
         const int64_t rg = rbeg + r;
         if (rg < j) continue;
-        // the row's multipliers: entry c gets x_c -= a0 f0_c (c > jj, when
-        // tau != 0), then x_c -= a1 f1_c (c > jj + 1, rows > j of a pair),
-        // the two updates of the column-by-column form in their order;
-        // a0 = v_j(r), a1 = v_{j+1}(r)
-        const bool do0 = tau != 0.0, do1 = two && rg > j;
-        double a0 = 0.0, a1 = 0.0;
+        // the row's reflector entries a[u] = v_{j+u}(r): zero above row j+u
+        // and past the group, one on row j+u, and below it the row's entry of
+        // column jj+u after the earlier reflectors of the group, times 1/scale
+        double a[kG];
         if (rg == j) {
-          a0 = tau != 0.0 ? 1.0 : 0.0;
-          if (ug == 0) X[jj * ldx + r] = beta;
-        } else if (tau != 0.0) {
-          a0 = xr0[q] * rs;
-          if (ug == 0) X[jj * ldx + r] = a0;
-          if (two) {
-            if (rg == j + 1) {
-              a1 = 1.0;
-            } else {
-              // column jj+1's entry after H_j (the same operation as its
-              // update below), then its reflector's entry
-              double y1r = xr1[q];
-              y1r -= sc[512 + 1] * a0;
-              a1 = y1r * rs1;
-            }
-          }
+          a[0] = tau[0] != 0.0 ? 1.0 : 0.0;
+          if (ug == 0) X[jj * ldx + r] = bet[0];
+        } else if (tau[0] != 0.0) {
+          a[0] = xg[q][0] * rsv[0];
+          if (ug == 0) X[jj * ldx + r] = a[0];
+        } else {
+          a[0] = 0.0;
+        }
+#pragma unroll
+        for (int u = 1; u < kG; ++u) {
+          double y = xg[q][u];
+#pragma unroll
+          for (int tt = 0; tt < u; ++tt) y -= sc[4 * kGW + tt * W + u] * a[tt];
+          a[u] = u >= ng || rg < j + u ? 0.0 : (rg == j + u ? 1.0 : y * rsv[u]);
         }
         // four columns at a time: loads first (clamped to the slab), then
-        // the updates, then the stores of the columns that exist
+        // the updates x_c -= f_tt,c a[tt] in the order of the column-by-column
+        // form, then the stores; a group column takes its R entry on its
+        // diagonal row and its reflector below it
         for (int c0 = jj + 1 + ug; c0 < ws; c0 += 4 * G) {
-          double xv[4], f0v[4], f1v[4];
+          double xv[4], fv[kG][4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = min(c0 + i * G, ws - 1);
             xv[i] = X[c * ldx + r];
-            f0v[i] = sc[512 + c - jj];
-            f1v[i] = sc[576 + c - jj];
+#pragma unroll
+            for (int tt = 0; tt < kG; ++tt) fv[tt][i] = sc[4 * kGW + tt * W + c - jj];
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = c0 + i * G;
-            if (do0) xv[i] -= f0v[i] * a0;
-            if (do1 && c > jj + 1) xv[i] -= f1v[i] * a1;
-          }
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int tt = 0; tt < kG; ++tt) xv[i] -= fv[tt][i] * a[tt];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int c = c0 + i * G;
-            if (c < ws) X[c * ldx + r] = xv[i];
+            const int c = c0 + i * G, u = c - jj;
+            if (c >= ws) continue;
+            double out = xv[i];
+#pragma unroll
+            for (int uu = 1; uu < kG; ++uu)
+              if (uu == u && uu < ng && rg >= j + uu) out = rg == j + uu ? bet[uu] : a[uu];
+            X[c * ldx + r] = out;
           }
         }
-        // the second reflector's column: R entry on row j + 1, v_{j+1} below
-        if (do1 && ug == 0) X[(jj + 1) * ldx + r] = rg == j + 1 ? beta1 : a1;
       }
       __syncthreads();
-      jj += two ? 2 : 1;
+      jj += ng;
     }
     if (!ok) break;
     // write the slab back (R and the stored vectors) and the explicit V;
@@ -554,7 +627,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 
 size_t panel_lds_doubles(int rpw, int nb) {
   const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded stride
-  return (size_t)W * ld + (size_t)W * nb + W * W + 640 + W;
+  return (size_t)W * ld + (size_t)W * nb + W * W + 5 * kGW + W;
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
@@ -700,7 +773,7 @@ int panel_config(int64_t mi, int nb, int *rpw) {
   }
 }
 
-size_t panel_part_doubles(int nwg, int nb) { return (size_t)2 * nwg * 4 * W + (size_t)nwg * W * nb; }
+size_t panel_part_doubles(int nwg, int nb) { return (size_t)2 * nwg * 2 * kGW + (size_t)nwg * W * nb; }
 
 hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
   int rpw = 0;
