@@ -841,11 +841,14 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
     // stream: C is final here (moved, not yet updated), and the panel does
     // not touch it
     const double *Gn = nullptr;
-    // workgroups of the auxiliary products: half the CUs, which leaves the
-    // panel (64) or the pivoted QR (at most 128) room plus slack for the
-    // main stream's short kernels (granting the products exactly what the
-    // persistent kernel leaves free measured 12 % slower overall)
-    const int beside_panel = h->ncu / 2, beside_qrcp = h->ncu / 2;
+    // Workgroups of the auxiliary products: those beside the panel take the
+    // CUs it leaves (the panel holds pw, one workgroup per CU, its LDS filling
+    // the CU), so that the next block's sample product ends with the panel
+    // rather than beside W; those beside the pivoted QR of the sketch (at
+    // most 128 workgroups) take half the CUs
+    int prw = 0;
+    const int pw = panel_config(mi, (int)bi, &prw);
+    const int beside_panel = pw > 0 && pw <= h->ncu / 2 ? h->ncu - pw : h->ncu / 2, beside_qrcp = h->ncu / 2;
     if constexpr (F32) if (pipe_next) {
       // FP32 storage (mixed): the BF16 sketch product of block i+1 from the
       // moved, not yet updated C, beside the panel

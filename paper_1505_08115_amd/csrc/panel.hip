@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     {
       // reduce-scatter: this workgroup sums elements [beg, end) over all
       // workgroups' partials; G threads share an element, thread g taking a
-      // contiguous range of workgroups with its loads issued 8 at a time, and
+      // contiguous range of workgroups with its loads issued 16 at a time, and
       // the G range sums are added in range order (a fixed order)
       const int E = ws * nz;
       const int per = (E + nwg - 1) / nwg;
@@ -471,12 +471,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
         const int e = e0 + t / G;
         double acc = 0.0;
         if (e < end)
-          for (int wb = w0; wb < w1; wb += 8) {
-            double x[8];
+          for (int wb = w0; wb < w1; wb += 16) {
+            double x[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = wb + u < w1 ? ld_agent(part_up + (size_t)(wb + u) * W * nb + e) : 0.0;
+            for (int u = 0; u < 16; ++u) x[u] = wb + u < w1 ? ld_agent(part_up + (size_t)(wb + u) * W * nb + e) : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += x[u];
+            for (int u = 0; u < 16; ++u) acc += x[u];
           }
         sc[t] = acc;
         __syncthreads();
@@ -491,21 +491,23 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
     ok = grid_sync(gb, gen, true, true);
     if (!ok) break;
     // the reduced rows V_s^T [V_s | A_rest] -> LDS (row tt at Wp + tt*nb,
-    // columns cs .. nb), 8 loads in flight
-    for (int base = 0; base < ws * nz; base += 8 * kPThreads) {
-      double x[8];
+    // columns cs .. nb), 16 loads in flight
+    for (int base = 0; base < ws * nz; base += 16 * kPThreads) {
+      double x[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int idx = base + t + u * kPThreads;
         x[u] = idx < ws * nz ? ld_agent(p.red + idx) : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int idx = base + t + u * kPThreads;
         if (idx < ws * nz) Wp[(idx / nz) * nb + cs + idx % nz] = x[u];
       }
     }
     for (int idx = ws * nb + t; idx < W * nb; idx += kPThreads) Wp[idx] = 0.0;   // rows ws .. W of a ragged slab
+    // the recurrence below reads rows of Wp that other waves stored
+    __syncthreads();
     // T_s by the recurrence T(r, tt) = -tau_tt sum_{r<=u<tt} T(r, u) v_u^T v_tt,
     // which involves only row r.  Eight lanes share a row (all 256 threads:
     // 32 rows x 8): lane `part` keeps T(r, u) for u = part + 8i in registers
@@ -631,128 +633,125 @@ size_t panel_lds_doubles(int rpw, int nb) {
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
-// matrix S = V^T V (Section 5.1), by blocks of W columns.  Row r of a
-// diagonal block follows the column recurrence T(r, j) = -tau_j
-// sum_{r<=u<j} T(r, u) S(u, j), T(j, j) = tau_j, which only involves row r
-// itself.  The block form T = [T_11, -T_11 S_12 T_22; 0, T_22] gives, for
-// block rows, T(I, J) = -(sum_{I<=K<J} T(I, K) S(K, J)) T(J, J): block row I
-// depends only on itself and the diagonal blocks.  So one workgroup owns
-// block row I: it computes the diagonal blocks T(J, J), J >= I, one row per
-// thread in registers, parks each in the LDS slot of its own block column,
-// then fills block columns I+1, I+2, ... from left to right, and writes the
-// whole block row (zeros left of the diagonal block) to T.
-// S(q, j) is read only for q < (J+1)*W, the part the panel kernel fills.
+// matrix S = V^T V (Section 5.1), by recursive doubling over blocks of W
+// columns.  A diagonal block follows the column recurrence T(r, j) = -tau_j
+// sum_{r<=u<j} T(r, u) S(u, j), T(j, j) = tau_j, which only involves row r.
+// Two neighbouring diagonal parts T_1 (columns [c0, c0+h)) and T_2 (columns
+// [c0+h, c0+2h)) combine as T = [T_1, -T_1 S_12 T_2; 0, T_2] (the product of
+// the two groups of reflectors), so one launch per level h = W, 2W, 4W, ...
+// fills the off-diagonal blocks of all pairs at once; each workgroup owns one
+// W x W tile (r, c) of one T_12 = -T_1 (S_12 T_2): it forms the column block
+// X = S_12 T_2(:, c) and then -T_1(r, :) X.  No grid-wide wait: a level only
+// reads the levels before it.  The strictly lower part of T is written as zero.
 constexpr int kTThreads = 256;
-constexpr int kTLd = W + 1;        // row stride of staged blocks of S (odd: no bank conflicts)
-constexpr int kTBlk = W * kTLd;    // one staged W x W block of S
+constexpr int kTLd = W + 1;        // row stride of staged W x W blocks (odd: no bank conflicts)
 
-__global__ __launch_bounds__(kTThreads) void wy_t_kernel(int nb, const double *__restrict__ tau,
-                                                         const double *__restrict__ S, double *__restrict__ T,
-                                                         int64_t ldt, int g1, int g2) {
+__global__ __launch_bounds__(kTThreads) void wy_t_diag_kernel(int nb, const double *__restrict__ tau,
+                                                              const double *__restrict__ S, double *__restrict__ T,
+                                                              int64_t ldt) {
+  __shared__ double Sd[W * kTLd];
+  const int t = threadIdx.x, J = blockIdx.x, cJ = J * W;
+  const int ws = min(W, nb - cJ);
+  for (int idx = t; idx < W * W; idx += kTThreads) {
+    const int u = idx % W, j = idx / W;
+    Sd[u * kTLd + j] = (u < ws && j < ws) ? S[(cJ + u) + (int64_t)(cJ + j) * nb] : 0.0;
+  }
+  // zeros left of the diagonal block (rows cJ .. cJ + ws)
+  for (int idx = t; idx < ws * cJ; idx += kTThreads) {
+    const int r = idx % ws, col = idx / ws;
+    T[(cJ + r) + (int64_t)col * ldt] = 0.0;
+  }
+  __syncthreads();
+  // eight lanes per row: lane `part` keeps T(r, u) for u = part + 8i and sums
+  // those terms; a group sum completes each entry
+  const int r = t >> 3, part = t & 7;
+  double tr[W / 8];
+#pragma unroll
+  for (int i = 0; i < W / 8; ++i) tr[i] = 0.0;
+#pragma unroll
+  for (int tt = 0; tt < W; ++tt) {
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < W / 8; ++i) {
+      const int u = part + 8 * i;
+      a += u < tt ? tr[i] * Sd[u * kTLd + tt] : 0.0;
+    }
+    a = group8_sum(a);
+    const double ta = tt < ws ? tau[cJ + tt] : 0.0;
+    const bool live = r < ws && tt < ws && tt >= r;
+    const double v = !live ? 0.0 : (tt == r ? ta : -ta * a);
+    if (part == (tt & 7)) tr[tt >> 3] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < W / 8; ++i) {
+    const int col = part + 8 * i;
+    if (r < ws && col < ws) T[(cJ + r) + (int64_t)(cJ + col) * ldt] = tr[i];
+  }
+}
+
+// One level of the doubling: h = W * 2^(level-1); workgroup -> (pair p, tile
+// row tr, tile column tc) of T_12 = T(c0 : c0+h, c0+h : c0+2h), c0 = 2 h p.
+// Entries past nb are zero in S, T and tau, so ragged edges need no cases
+// beyond the bounds of the loads and stores.
+template <int RPT>   // rows of X per thread: h / 8
+__global__ __launch_bounds__(kTThreads) void wy_t_level_kernel(int nb, const double *__restrict__ S,
+                                                               double *__restrict__ T, int64_t ldt) {
   extern __shared__ double sh[];
+  constexpr int h = 8 * RPT;
   const int t = threadIdx.x;
-  const int nslab = (nb + W - 1) / W;
-  const int I = blockIdx.x, cI = I * W;
-  const int ldr = nslab * W + 1;              // row stride of the block row (odd: no bank conflicts)
-  double *R = sh;                             // W x ldr: block row I, column c at R[r*ldr + c - cI]
-  double *Acc = R + (size_t)W * ldr;          // W x (W+1)
-  double *taul = Acc + W * (W + 1);           // nslab*W: tau, zero past nb
-  double *St = taul + nslab * W;              // staging of S
-  for (int i = t; i < nslab * W; i += kTThreads) taul[i] = i < nb ? tau[i] : 0.0;
-  auto Sg = [&](int q, int j) -> double { return (q < nb && j < nb) ? S[q + (int64_t)j * nb] : 0.0; };
-
-  // 1. diagonal blocks J >= I, g1 at a time: thread (g, r) owns row r of block I + round*g1 + g
-  for (int J0 = I; J0 < nslab; J0 += g1) {
-    const int ng = min(g1, nslab - J0);
+  const int nt = h / W;                       // tiles per side of T_12
+  const int p = blockIdx.x / (nt * nt), tr = (blockIdx.x / nt) % nt, tc = blockIdx.x % nt;
+  const int c0 = 2 * h * p, c1 = c0 + h;      // T_1 columns [c0, c1), T_2 columns [c1, c1 + h)
+  if (c1 >= nb) return;                       // no right half: nothing to combine
+  double *X = sh;                             // h x W: X = S_12 T_2(:, tile tc), row i at X + i*kTLd
+  double *Bs = X + (size_t)h * kTLd;          // W x W staged block of T_2, then of T_1
+  double *As = Bs + W * kTLd;                 // h x W staged block column of S_12
+  auto Tg = [&](int i, int j) -> double { return (i < nb && j < nb) ? T[i + (int64_t)j * ldt] : 0.0; };
+  auto Sg = [&](int i, int j) -> double { return (i < nb && j < nb) ? S[i + (int64_t)j * nb] : 0.0; };
+  // X(i, cc) = sum_{b <= tc} sum_k S_12(i, W b + k) T_2(W b + k, W tc + cc): thread (row group, column cc)
+  const int cc = t & (W - 1), rg = t >> 5;    // 8 row groups of RPT rows
+  double acc[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+  for (int bb = 0; bb <= tc; ++bb) {
     __syncthreads();
-    // S is column-major: consecutive threads read consecutive rows u (coalesced), 8 loads in flight
-    for (int base = 0; base < ng * W * W; base += 8 * kTThreads) {
-      double x[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = base + t + q * kTThreads;
-        const int g = idx / (W * W), jj = (idx / W) % W, u = idx % W, cJ = (J0 + g) * W;
-        x[q] = idx < ng * W * W ? Sg(cJ + u, cJ + jj) : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = base + t + q * kTThreads;
-        const int g = idx / (W * W), jj = (idx / W) % W, u = idx % W;
-        if (idx < ng * W * W) St[(size_t)g * kTBlk + u * kTLd + jj] = x[q];
-      }
+    for (int idx = t; idx < W * W; idx += kTThreads) {
+      const int k = idx % W, j = idx / W;
+      Bs[k * kTLd + j] = Tg(c1 + W * bb + k, c1 + W * tc + j);
+    }
+    for (int idx = t; idx < h * W; idx += kTThreads) {
+      const int i = idx % h, k = idx / h;
+      As[i * kTLd + k] = Sg(c0 + i, c1 + W * bb + k);
     }
     __syncthreads();
-    for (int task = t; task < ng * W; task += kTThreads) {
-      const int g = task / W, r = task % W, J = J0 + g, cJ = J * W;
-      const double *sj = St + (size_t)g * kTBlk;
-      double *d = R + (size_t)r * ldr + (cJ - cI);   // row r of T(J, J), built in place
-      for (int jj = 0; jj < W; ++jj) {
-        const double tj = taul[cJ + jj];
-        double acc = 0.0;
-#pragma unroll 4
-        for (int u = r; u < jj; ++u) acc += d[u] * sj[u * kTLd + jj];
-        d[jj] = jj < r ? 0.0 : (jj == r ? tj : -tj * acc);
-      }
+    for (int k = 0; k < W; ++k) {
+      const double bv = Bs[k * kTLd + cc];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) acc[q] += As[(rg * RPT + q) * kTLd + k] * bv;
     }
   }
-  __syncthreads();
-  // 2. block columns J > I: Acc = sum_K T(I, K) S(K, J), then T(I, J) = -Acc T(J, J)
-  const int c = t & (W - 1), rq = t >> 5;     // thread: column c, rows 4 rq .. 4 rq + 3
-  for (int J = I + 1; J < nslab; ++J) {
-    const int cJ = J * W;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int K0 = I; K0 < J; K0 += g2) {
-      const int nk = min(g2, J - K0);
-      __syncthreads();
-      // rows q of the chunk fastest (coalesced reads of S), 8 loads in flight
-      for (int base = 0; base < nk * W * W; base += 8 * kTThreads) {
-        double x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = base + t + u * kTThreads;
-          const int cc = idx / (nk * W), q = idx % (nk * W);
-          x[u] = idx < nk * W * W ? Sg(K0 * W + q, cJ + cc) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int idx = base + t + u * kTThreads;
-          const int cc = idx / (nk * W), q = idx % (nk * W);
-          if (idx < nk * W * W) St[(size_t)q * kTLd + cc] = x[u];
-        }
-      }
-      __syncthreads();
-      const double *r0 = R + (size_t)(4 * rq) * ldr + (K0 * W - cI);
-#pragma unroll 8
-      for (int q = 0; q < nk * W; ++q) {
-        const double sv = St[(size_t)q * kTLd + c];
-        a0 += r0[q] * sv;
-        a1 += r0[ldr + q] * sv;
-        a2 += r0[2 * ldr + q] * sv;
-        a3 += r0[3 * ldr + q] * sv;
-      }
-    }
-    Acc[(4 * rq + 0) * (W + 1) + c] = a0;
-    Acc[(4 * rq + 1) * (W + 1) + c] = a1;
-    Acc[(4 * rq + 2) * (W + 1) + c] = a2;
-    Acc[(4 * rq + 3) * (W + 1) + c] = a3;
+  for (int q = 0; q < RPT; ++q) X[(rg * RPT + q) * kTLd + cc] = acc[q];
+  // tile (tr, tc) of T_12 = -sum_{a >= tr} T_1(W tr + i, W a + k) X(W a + k, cc): thread (rows 4 rq .. 4 rq + 3, cc)
+  const int rq = t >> 5;
+  double o[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int a = tr; a < nt; ++a) {
     __syncthreads();
-    const double *dj = R + (cJ - cI);          // T(J, J) parked in this slot: row u at dj + u*ldr
-    double o[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int u = 0; u <= c; ++u) {
-      const double dv = dj[(size_t)u * ldr + c];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] += Acc[(4 * rq + q) * (W + 1) + u] * dv;
+    for (int idx = t; idx < W * W; idx += kTThreads) {
+      const int i = idx % W, k = idx / W;
+      Bs[i * kTLd + k] = Tg(c0 + W * tr + i, c0 + W * a + k);
     }
     __syncthreads();
+    for (int k = 0; k < W; ++k) {
+      const double xv = X[(W * a + k) * kTLd + cc];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) R[(size_t)(4 * rq + q) * ldr + (cJ - cI) + c] = -o[q];
+      for (int q = 0; q < 4; ++q) o[q] += Bs[(4 * rq + q) * kTLd + k] * xv;
+    }
   }
-  __syncthreads();
-  // 3. write block row I: zeros left of the diagonal block
-  const int wsI = min(W, nb - cI);
-  for (int idx = t; idx < W * nb; idx += kTThreads) {
-    const int r = idx % W, col = idx / W;
-    if (r < wsI) T[(cI + r) + (int64_t)col * ldt] = col < cI ? 0.0 : R[(size_t)r * ldr + (col - cI)];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = c0 + W * tr + 4 * rq + q, j = c1 + W * tc + cc;
+    if (i < nb && j < nb) T[i + (int64_t)j * ldt] = -o[q];
   }
 }
 
@@ -797,24 +796,32 @@ hipError_t launch_wy_t(hipStream_t s, int nb, const double *tau, const double *S
   if (nb <= 0) return hipSuccess;
   if (nb > 512) return hipErrorInvalidValue;
   const int nslab = (nb + W - 1) / W;
-  const size_t fixed = (size_t)W * (nslab * W + 1) + W * (W + 1) + (size_t)nslab * W;   // the kernel's layout
-  if (fixed + kTBlk > kLdsDoubles) return hipErrorInvalidValue;
-  const size_t room = kLdsDoubles - fixed;
-  int g1 = (int)(room / kTBlk), g2 = (int)(room / kTBlk);
-  g1 = g1 > kTThreads / W ? kTThreads / W : g1;
-  g1 = g1 > nslab ? nslab : g1;
-  g2 = g2 > nslab ? nslab : g2;
-  const size_t stage = (size_t)(g1 > g2 ? g1 : g2) * kTBlk;
-  const size_t bytes = (fixed + stage) * sizeof(double);
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void *)wy_t_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kLdsDoubles * sizeof(double)));
+  hipLaunchKernelGGL(wy_t_diag_kernel, dim3(nslab), dim3(kTThreads), 0, s, nb, tau, S, T, ldt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int h = W; h < nb; h *= 2) {
+    const int nt = h / W, npair = (nb + 2 * h - 1) / (2 * h);
+    const size_t lds = ((size_t)h * kTLd + W * kTLd + (size_t)h * kTLd) * sizeof(double);
+    const void *fn = h == W ? (const void *)wy_t_level_kernel<W / 8>
+                   : h == 2 * W ? (const void *)wy_t_level_kernel<2 * W / 8>
+                   : h == 4 * W ? (const void *)wy_t_level_kernel<4 * W / 8>
+                                : (const void *)wy_t_level_kernel<8 * W / 8>;
+    static bool attr_done[4] = {false, false, false, false};
+    const int li = h == W ? 0 : h == 2 * W ? 1 : h == 4 * W ? 2 : 3;
+    if (!attr_done[li]) {
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsDoubles * sizeof(double)));
+      if (e != hipSuccess) return e;
+      attr_done[li] = true;
+    }
+    const dim3 grid((unsigned)(npair * nt * nt)), block(kTThreads);
+    if (li == 0) hipLaunchKernelGGL(wy_t_level_kernel<W / 8>, grid, block, lds, s, nb, S, T, ldt);
+    else if (li == 1) hipLaunchKernelGGL(wy_t_level_kernel<2 * W / 8>, grid, block, lds, s, nb, S, T, ldt);
+    else if (li == 2) hipLaunchKernelGGL(wy_t_level_kernel<4 * W / 8>, grid, block, lds, s, nb, S, T, ldt);
+    else hipLaunchKernelGGL(wy_t_level_kernel<8 * W / 8>, grid, block, lds, s, nb, S, T, ldt);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    attr_done = true;
   }
-  hipLaunchKernelGGL(wy_t_kernel, dim3(nslab), dim3(kTThreads), bytes, s, nb, tau, S, T, ldt, g1, g2);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace rq
