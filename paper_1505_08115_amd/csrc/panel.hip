@@ -15,9 +15,9 @@
 //     follows from the reduced sums alone: v^T x_c = (g_c - beta x_c(j)) /
 //     (alpha - beta).  Degenerate columns follow the conventions of the
 //     oracle: tau = 0 for a zero column or a column of length one.  Up to
-//     four columns share one exchange: the reflectors leave inner products
+//     kG = 8 columns share one exchange: the reflectors leave inner products
 //     over rows >= j unchanged, so the sums of x_{j+u}^T x_c and the entries
-//     of rows j .. j+3 determine all four reflectors and their action.
+//     of rows j .. j+7 determine all eight reflectors and their action.
 //   * after a slab: the partial products V_s^T [V_s | A_rest] are
 //     reduce-scattered (two barriers); they give the slab's Gram block
 //     V_s^T V_s for its T_s and W = V_s^T A_rest, which updates the rest of
@@ -36,7 +36,7 @@ constexpr int W = kPanelW;
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kPThreads = 256;
 constexpr size_t kLdsDoubles = 20480 - 256;
-constexpr int kG = 4;                       // columns per exchange in a column step
+constexpr int kG = 8;                       // columns per exchange in a column step
 constexpr int kGW = kG * W;                 // sums (or row entries) per exchange
 constexpr int kNH = kPThreads / kGW;        // workgroup sets in the reduction of the sums
 constexpr int kLd = (64 + kNH - 1) / kNH;   // loads in flight per thread in that reduction
