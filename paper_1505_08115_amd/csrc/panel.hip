@@ -50,13 +50,14 @@ __device__ void flag_nonfinite(int32_t *info, int block_index) {
 
 __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw, GridBarrier gb) {
   extern __shared__ double lds[];
+  __shared__ double sc_st[5 * kGW + W];     // a separate array: its accesses never alias the slab's
   const int nb = p.nb;
   const int rpw4 = (rpw + 3) & ~3;           // rows padded to the MFMA K step
   const int ldx = rpw4 + 1;                 // odd stride: the 16 lanes of a fragment hit distinct banks
   double *X = lds;                          // W x ldx   slab (own rows), column c at X + c*ldx
   double *Wp = X + (size_t)W * ldx;         // W x nb    reduced V_s^T [V_s | A_rest], row t at Wp + t*nb (columns >= cs)
   double *Ts = Wp + (size_t)W * nb;         // W x W     column-major
-  double *sc = Ts + W * W;                  // 5 kGW     reduction scratch
+  double *sc = sc_st;                       // 5 kGW     reduction scratch
   double *taus = sc + 5 * kGW;              // W
 
   const int nwg = gridDim.x, wg = blockIdx.x, t = threadIdx.x;
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 
 size_t panel_lds_doubles(int rpw, int nb) {
   const size_t ld = (size_t)((rpw + 3) & ~3) + 1;   // the kernel's padded stride
-  return (size_t)W * ld + (size_t)W * nb + W * W + 5 * kGW + W;
+  return (size_t)W * ld + (size_t)W * nb + W * W;
 }
 
 // T (nb x nb, upper triangular) of the compact WY form from tau and the Gram
@@ -765,7 +766,7 @@ int panel_config(int64_t mi, int nb, int *rpw) {
     if (nwg > 256) return 0;
     const int64_t r = (mi + nwg - 1) / nwg;
     // the row update of a column step gives a thread at most two rows
-    if (r <= 2 * kPThreads && panel_lds_doubles((int)r, nb) <= kLdsDoubles) {
+    if (r <= 2 * kPThreads && panel_lds_doubles((int)r, nb) <= kLdsDoubles - (5 * kGW + W)) {
       *rpw = (int)r;
       return (int)((mi + r - 1) / r);
     }
@@ -781,7 +782,7 @@ hipError_t launch_panel_qr(hipStream_t s, const PanelQR &p) {
   static bool attr_done = false;
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute((const void *)panel_qr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kLdsDoubles * sizeof(double)));
+                                       (int)((kLdsDoubles - (5 * kGW + W)) * sizeof(double)));
     if (e != hipSuccess) return e;
     attr_done = true;
   }
