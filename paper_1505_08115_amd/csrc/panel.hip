@@ -42,6 +42,11 @@ constexpr int kNH = kPThreads / kGW;        // workgroup sets in the reduction o
 constexpr int kLd = (64 + kNH - 1) / kNH;   // loads in flight per thread in that reduction
 static_assert(kPThreads % kGW == 0 && 2 * kGW % 64 == 0, "column-step layout");
 
+// lane l's value in every lane (l wave-uniform)
+__device__ __forceinline__ double lane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l), __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
 __device__ void flag_nonfinite(int32_t *info, int block_index) {
   if (!info) return;
   atomicExch(&info[0], 1);
@@ -204,22 +209,32 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
       double bet[kG], tau[kG], rsv[kG];
       int ng = 1;
       {
-        const int tc = min(t, W - 1);
-        double zg[kG][kG], zc[kG], vq[kG], rr[kG];
+        // Lane l of every 8-lane group keeps group column l & 7 (its entries
+        // zo on rows j .. j+kG-1 and its sums gmo); reflector tt's data come
+        // from lane tt by readlane, so a lane updates only its own group
+        // column instead of all of them.  Every lane then takes the same
+        // decisions from the same broadcast values.
+        const int tc = min(t, W - 1), gl = t & 7;
+        double zo[kG], gmo[kG], zc[kG], gmc[kG], vq[kG], rr[kG];
 #pragma unroll
         for (int s2 = 0; s2 < kG; ++s2) {
           zc[s2] = sc[kGW + s2 * W + tc];
-#pragma unroll
-          for (int u = 0; u < kG; ++u) zg[u][s2] = sc[kGW + s2 * W + u];
+          gmc[s2] = sc[s2 * W + tc];
+          zo[s2] = sc[kGW + s2 * W + gl];
+          gmo[s2] = sc[s2 * W + gl];
         }
         bool open = true;
 #pragma unroll
         for (int tt = 0; tt < kG; ++tt) {
-          // reflector tt from column tt after the earlier ones
+          // reflector tt from column tt after the earlier ones (lane tt's copy)
+          double pz[kG];
+#pragma unroll
+          for (int s2 = 0; s2 < kG; ++s2) pz[s2] = lane_d(zo[s2], tt);
+          const double guu = lane_d(gmo[tt], tt);
           bool act;
           double scale;
           if (tt == 0) {
-            const double alpha = zg[0][0], nrm2 = sc[0];
+            const double alpha = pz[0], nrm2 = guu;
             bet[0] = alpha;
             tau[0] = 0.0;
             scale = 1.0;
@@ -239,13 +254,12 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
             // column tt joins while its norm over rows >= j+tt, Gm_tt,tt minus
             // the squares of its R entries, keeps more than half of Gm_tt,tt
             // (relative error below 2 u); otherwise it takes a step of its own
-            const double guu = sc[tt * W + tt];
             double nrm = guu;
 #pragma unroll
-            for (int s2 = 0; s2 < tt; ++s2) nrm -= zg[tt][s2] * zg[tt][s2];
+            for (int s2 = 0; s2 < tt; ++s2) nrm -= pz[s2] * pz[s2];
             act = open && tt < gc && guu > 0.0 && guu < 1.79e308 && nrm > 0.5 * guu;
             open = act;
-            const double y = zg[tt][tt];
+            const double y = pz[tt];
             const double b = (y >= 0.0 ? -1.0 : 1.0) * sqrt(act ? nrm : 1.0);
             bet[tt] = act ? b : 0.0;
             tau[tt] = act ? (b - y) / b : 0.0;
@@ -257,23 +271,23 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
           rsv[tt] = 1.0 / scale;
 #pragma unroll
           for (int s2 = 0; s2 < kG; ++s2) {
-            rr[s2] = s2 < tt ? zg[tt][s2] : 0.0;
-            vq[s2] = s2 > tt ? zg[tt][s2] * rsv[tt] : 0.0;
+            rr[s2] = s2 < tt ? pz[s2] : 0.0;
+            vq[s2] = s2 > tt ? pz[s2] * rsv[tt] : 0.0;
           }
-          // reflector tt on the later group columns and on column jj + t
+          // reflector tt on this lane's group column (when it lies past tt)
+          // and on column jj + t
+          {
+            double ip = gmo[tt];
 #pragma unroll
-          for (int u = tt + 1; u < kG; ++u) {
-            double ip = sc[tt * W + u];
+            for (int s2 = 0; s2 < tt; ++s2) ip -= rr[s2] * zo[s2];
+            double f = tau[tt] * ((ip - bet[tt] * zo[tt]) * rsv[tt]);
+            f = act && gl > tt ? f : 0.0;
+            zo[tt] -= f;
 #pragma unroll
-            for (int s2 = 0; s2 < tt; ++s2) ip -= rr[s2] * zg[u][s2];
-            double f = tau[tt] * ((ip - bet[tt] * zg[u][tt]) * rsv[tt]);
-            f = act ? f : 0.0;
-            zg[u][tt] -= f;
-#pragma unroll
-            for (int s2 = tt + 1; s2 < kG; ++s2) zg[u][s2] -= f * vq[s2];
+            for (int s2 = tt + 1; s2 < kG; ++s2) zo[s2] -= f * vq[s2];
           }
           {
-            double ip = sc[tt * W + tc];
+            double ip = gmc[tt];
 #pragma unroll
             for (int s2 = 0; s2 < tt; ++s2) ip -= rr[s2] * zc[s2];
             double f = tau[tt] * ((ip - bet[tt] * zc[tt]) * rsv[tt]);
