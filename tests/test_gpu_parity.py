@@ -187,10 +187,12 @@ def _compare_T(Fz, ref, b):
         assert np.all(np.tril(Tgi, -1) == 0.0), f"T block {i} is not upper triangular"
 
 
-@pytest.mark.parametrize("m,n,b,p", [(300, 250, 80, 6), (384, 384, 64, 8), (520, 500, 96, 4)])
+@pytest.mark.parametrize("m,n,b,p", [(300, 250, 80, 6), (384, 384, 64, 8), (520, 500, 96, 4), (1100, 1000, 300, 8),
+                                     (1200, 1100, 512, 0)])
 def test_T_blocks_multi_slab_and_ragged(m, n, b, p):
     # b spans several 32-column slabs of the panel kernel, b = 80 and the
-    # last blocks are ragged (250 = 3*80 + 10, 500 = 5*96 + 20)
+    # last blocks are ragged (250 = 3*80 + 10, 500 = 5*96 + 20); b = 300 and
+    # 512 take every level of the T factor's doubling (32 to 256 columns)
     A = W.make_matrix(m, n, W.sigma_geometric(n, 3.0), seed=7 + b).numpy()
     blocks = _oracle_G(5, m, n, b, p, n, True)
     ref = O.rqrcp(A, b, p, seed=5, G=blocks)
