@@ -279,6 +279,7 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
     if (P.diag) gpart = std::max(gpart, gemm_part_doubles(r0, bi, bi));   // A12 V'
     if (ni > bi) {
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, mi));
+      gpart = std::max(gpart, gemm_part_doubles(bi, ni, mi));        // [S | W] = V^T [V | C]
       gpart = std::max(gpart, gemm_part_doubles(mi, ni - bi, bi));
       gpart = std::max(gpart, gemm_part_doubles(bi, ni - bi, bi));   // T^T W and U'^T C
       gpart32 = std::max(gpart32, gemm_part_doubles(bi, ni - bi, mi));
@@ -317,9 +318,11 @@ rqrcp_status_t make_plan(rqrcp_handle_t h, rqrcp_dtype_t dt, int64_t m, int64_t 
   P.Vb = w.take((size_t)m * P.b * d);
   P.VT = w.take((size_t)m * P.b * d);
   P.Vt = w.take((size_t)m * P.b * d);
-  P.Wb = w.take((size_t)P.b * n * d);
+  // S (b x b) directly in front of W (b x n): at b = 256 one launch forms
+  // [S | W] = V^T [V | C] with leading dimension b
+  P.Sg = w.take((size_t)P.b * (P.b + n) * d);
+  P.Wb = P.Sg + (size_t)P.b * P.b * d;
   P.gpart = w.take(gpart * d);
-  P.Sg = w.take((size_t)P.b * P.b * d);
   P.ppart = w.take(ppart * d);
   P.pred = w.take((size_t)kPanelW * P.b * d);
   P.qrec = w.take(qrcp_small_rec_doubles(qnwg) * d);
@@ -957,28 +960,42 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
       // (G V(b_i:, :)) (T^T W), whose first factor needs only V and runs on
       // the auxiliary stream beside W; no V T^T is formed
       const bool reassoc = !F32;
-      CHK(hipEventRecord(h->fork_ev, s), "fork event");
-      CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
-      {
-        ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
-        CHK(launch_gram(h->side, Vb, mi, mi, bi, Sg, vtpart), "V^T V");
-        CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
+      // At b = 256 in FP64, S = V^T V comes from W's own launch as two more
+      // 128-column tiles ([S | W] = V^T [V | C], S directly in front of W):
+      // nothing can share a CU with W's workgroups, so S beside W on the side
+      // stream waited for W's last workgroups, and T after it
+      const bool fuse_s = reassoc && bi == b && b == 256;
+      if (!fuse_s) {
+        CHK(hipEventRecord(h->fork_ev, s), "fork event");
+        CHK(hipStreamWaitEvent(h->side, h->fork_ev, 0), "side stream wait");
+        {
+          ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi, h->side);
+          CHK(launch_gram(h->side, Vb, mi, mi, bi, Sg, vtpart), "V^T V");
+          CHK(launch_wy_t(h->side, (int)bi, tau + r0, Sg, Ti, b), "T factor");
+        }
+        if (!reassoc) {
+          // V T^T right after T, also beside W (its own split-K buffer)
+          ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi), h->side);
+          GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
+          CHK(launch_gemm_f64(h->side, gv, vtpart), "V T^T");
+          if constexpr (F32) CHK(launch_copy_f64_f32(h->side, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
+        }
+        CHK(hipEventRecord(h->join_ev, h->side), "join event");
       }
-      if (!reassoc) {
-        // V T^T right after T, also beside W (its own split-K buffer)
-        ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * mi * bi * bi, 8.0 * (2.0 * mi * bi + bi * bi), h->side);
-        GemmF64 gv{false, true, mi, bi, bi, Vb, mi, Ti, b, Vt, mi, 1.0, 0.0};
-        CHK(launch_gemm_f64(h->side, gv, vtpart), "V T^T");
-        if constexpr (F32) CHK(launch_copy_f64_f32(h->side, Vt, mi, Vt32, mi, mi, bi), "V T^T to FP32");
-      }
-      CHK(hipEventRecord(h->join_ev, h->side), "join event");
       {
         ScopedTimer t2(h, RQRCP_K_W_GEMM, 2.0 * bi * nc * mi,
                        (double)sizeof(T) * (mi * nc + mi * bi + bi * nc));
         if constexpr (!F32) {
-          GemmF64 gw{false, false, bi, ni - bi, mi, VT, b, C, lda, Wb, bi, 1.0, 0.0};
-          gw.wprod = true;
-          CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
+          if (fuse_s) {
+            GemmF64 gw{false, false, bi, ni, mi, VT, b, C, lda, Sg, bi, 1.0, 0.0};
+            gw.wprod = true;
+            gw.B2 = Vb; gw.ldb2 = mi; gw.n2 = bi;
+            CHK(launch_gemm_f64(s, gw, gpart), "V^T [V | C]");
+          } else {
+            GemmF64 gw{false, false, bi, ni - bi, mi, VT, b, C, lda, Wb, bi, 1.0, 0.0};
+            gw.wprod = true;
+            CHK(launch_gemm_f64(s, gw, gpart), "V^T C");
+          }
         } else {
           CHK(launch_copy_f64_f32(s, VT, b, VT32, b, bi, mi), "V^T to FP32");
           GemmF32 gw{false, false, bi, ni - bi, mi, VT32, b, C, lda, W32, bi, 1.f, 0.f};
@@ -997,7 +1014,12 @@ rqrcp_status_t factor_impl(rqrcp_handle_t h, const FactorPlan &P, const rqrcp_op
           CHK(launch_gemm_f64(aux, g1, gpart_aux), "G V");
           CHK(hipEventRecord(h->ev_ypre, aux), "correction factor event");
         }
-      CHK(hipStreamWaitEvent(s, h->join_ev, 0), reassoc ? "join T" : "join T and V T^T");
+      if (fuse_s) {
+        ScopedTimer tt(h, RQRCP_K_TFACTOR, (double)bi * bi * bi / 3.0, 16.0 * bi * bi);
+        CHK(launch_wy_t(s, (int)bi, tau + r0, Sg, Ti, b), "T factor");
+      } else {
+        CHK(hipStreamWaitEvent(s, h->join_ev, 0), reassoc ? "join T" : "join T and V T^T");
+      }
       if constexpr (!F32) {
         ScopedTimer t1(h, RQRCP_K_VT_GEMM, 2.0 * bi * bi * nc, 8.0 * (bi * bi + 2.0 * bi * nc));
         GemmF64 gw2{true, false, bi, ni - bi, bi, Ti, b, Wb, bi, W2, bi, 1.0, 0.0};

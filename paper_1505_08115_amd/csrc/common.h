@@ -217,6 +217,10 @@ struct Gemm {
   int max_wg = 0;          // > 0: at most this many workgroups (each loops over tiles), so that a
                            // product on a side stream leaves CUs free for persistent kernels
   bool wprod = false;      // the factorization's W = V^T C (a separate kernel name in profiles)
+  // n2 > 0 (W with S = V^T V fused in front): the first n2 columns of op(B)
+  // come from B2 (ld ldb2), column n2 + j from column j of B
+  const T *B2 = nullptr;
+  int64_t ldb2 = 0, n2 = 0;
 };
 typedef Gemm<double> GemmF64;
 typedef Gemm<float> GemmF32;

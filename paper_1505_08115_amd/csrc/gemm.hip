@@ -79,7 +79,7 @@ template <typename T, int BM, int BN, bool TA, bool TB, bool SPLIT, int NT = 256
 __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64_t kchunk, const T *__restrict__ A,
                                           int64_t lda, const T *__restrict__ B, int64_t ldb, T *__restrict__ C,
                                           int64_t ldc, T alpha, T beta, T *__restrict__ partial, int64_t m0,
-                                          int64_t n0) {
+                                          int64_t n0, int64_t nb0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int WGN = NT / 64 / WGM;
   constexpr int WBM = BM / WGM, WBN = BN / WGN;   // one wave's block
@@ -107,7 +107,7 @@ __device__ __forceinline__ void gemm_tile(int64_t M, int64_t N, int64_t K, int64
   T ra[AE], rb[BE];
   auto load = [&](int64_t k0) {
     const T *pa = TA ? A + (k0 + a_k) + (m0 + a_i) * lda : A + (m0 + a_i) + (k0 + a_k) * lda;
-    const T *pb = TB ? B + (n0 + b_j) + (k0 + b_k) * ldb : B + (k0 + b_k) + (n0 + b_j) * ldb;
+    const T *pb = TB ? B + (nb0 + b_j) + (k0 + b_k) * ldb : B + (k0 + b_k) + (nb0 + b_j) * ldb;
     if (interior && (AL || k0 + kBK <= kend)) {
 #pragma unroll
       for (int q = 0; q < AE; ++q) ra[q] = pa[q * a_step];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int64_t M, int64_t N, int6
                                                       T *__restrict__ C, int64_t ldc, T alpha,
                                                       T beta, T *__restrict__ partial) {
   gemm_tile<T, BM, BN, TA, TB, SPLIT>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
-                                      (int64_t)blockIdx.x * BM, (int64_t)blockIdx.y * BN);
+                                      (int64_t)blockIdx.x * BM, (int64_t)blockIdx.y * BN, (int64_t)blockIdx.y * BN);
 }
 
 // A capped grid: each workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x,
@@ -242,11 +242,18 @@ __global__ __launch_bounds__(NT, 1) void gemm_kernel_capped(int64_t M, int64_t N
                                                             const T *__restrict__ A, int64_t lda,
                                                             const T *__restrict__ B, int64_t ldb,
                                                             T *__restrict__ C, int64_t ldc, T alpha,
-                                                            T beta, T *__restrict__ partial) {
+                                                            T beta, T *__restrict__ partial,
+                                                            const T *__restrict__ B2 = nullptr, int64_t ldb2 = 0,
+                                                            int64_t n2 = 0) {
   const int64_t ntm = (M + BM - 1) / BM, ntiles = ntm * ((N + BN - 1) / BN);
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    gemm_tile<T, BM, BN, TA, TB, SPLIT, NT, WGM, AL>(M, N, K, kchunk, A, lda, B, ldb, C, ldc, alpha, beta, partial,
-                                                     (tile % ntm) * BM, (tile / ntm) * BN);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // columns below n2 (a multiple of BN) come from B2, the others from B
+    const int64_t n0 = (tile / ntm) * BN;
+    const bool first = n0 < n2;
+    gemm_tile<T, BM, BN, TA, TB, SPLIT, NT, WGM, AL>(M, N, K, kchunk, A, lda, first ? B2 : B, first ? ldb2 : ldb, C,
+                                                     ldc, alpha, beta, partial, (tile % ntm) * BM, n0,
+                                                     first ? n0 : n0 - n2);
+  }
 }
 
 // Short, wide products C (M x N) = alpha op(A) B + beta C with M <= 448 (the
@@ -584,7 +591,8 @@ hipError_t launch_w256(hipStream_t s, const Gemm<T> &g, int splits, int64_t kchu
     const bool al = g.N % 128 == 0 && g.K % kBK == 0 && kchunk % kBK == 0;
 #define RQ_W256(SP, AL)                                                                                              \
     hipLaunchKernelGGL((gemm_kernel_capped<T, 256, 128, false, false, SP, kTagW, 512, 4, AL>), grid, dim3(512), 0, \
-                       s, g.M, g.N, g.K, kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial)
+                       s, g.M, g.N, g.K, kchunk, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.alpha, g.beta, partial,   \
+                       g.B2, g.ldb2, g.n2)
     if (splits > 1) {
       if (al) RQ_W256(true, true);
       else RQ_W256(true, false);
@@ -616,7 +624,9 @@ hipError_t launch_gemm(hipStream_t s, const Gemm<T> &g, T *partial) {
   else split_plan(g, &splits, &kchunk);
   if (g.K <= 0) splits = 1;
   hipError_t e;
-  if (sizeof(T) == 8 && rows && g.wprod && g.M == 256 && g.max_wg == 0) e = launch_w256(s, g, splits, kchunk, partial);
+  const bool w256 = sizeof(T) == 8 && rows && g.wprod && g.M == 256 && g.max_wg == 0;
+  if (g.n2 != 0 && (!w256 || g.n2 < 0 || g.n2 % 128 != 0 || g.n2 > g.N || g.B2 == nullptr)) return hipErrorInvalidValue;
+  if (w256) e = launch_w256(s, g, splits, kchunk, partial);
   else if (rows) e = launch_rows<T, false>(s, g, splits, kchunk, partial);
   else if (!g.ta && !g.tb) e = launch_shape<T, false, false>(s, g, splits, kchunk, partial);
   else if (g.ta && !g.tb) e = launch_shape<T, true, false>(s, g, splits, kchunk, partial);
