@@ -220,7 +220,7 @@ def test_orthonormal_completion_with_noise_across_the_threshold(m, n, b, r):
 
 @pytest.mark.parametrize("q", [1, 2])
 def test_method_3_on_C3s_at_block_256(q):
-    """blockRRQR at the survey's block size on C3's 1024^2 subcase (singular
+    """blockRRQR at block size 256 on C3's 1024^2 subcase (singular
     values 1/j, a 1e-6 gap after 256): four blocks of 256, each triangle
     diagonalised by the cooperative Jacobi kernel.  D holds the singular
     values of A restricted to the span that a block's sketch picks, so it does
