@@ -667,9 +667,19 @@ __global__ __launch_bounds__(kTThreads) void wy_t_diag_kernel(int nb, const doub
   __shared__ double Sd[W * kTLd];
   const int t = threadIdx.x, J = blockIdx.x, cJ = J * W;
   const int ws = min(W, nb - cJ);
-  for (int idx = t; idx < W * W; idx += kTThreads) {
-    const int u = idx % W, j = idx / W;
-    Sd[u * kTLd + j] = (u < ws && j < ws) ? S[(cJ + u) + (int64_t)(cJ + j) * nb] : 0.0;
+  // every staged entry is loaded before any is written to LDS, so the loads
+  // are in flight together (a write after each load would wait for it)
+  static_assert(W * W % kTThreads == 0, "staging loops without a tail");
+  double sv[W * W / kTThreads];
+#pragma unroll
+  for (int q = 0; q < W * W / kTThreads; ++q) {
+    const int idx = t + q * kTThreads, u = idx % W, j = idx / W;
+    sv[q] = (u < ws && j < ws) ? S[(cJ + u) + (int64_t)(cJ + j) * nb] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < W * W / kTThreads; ++q) {
+    const int idx = t + q * kTThreads;
+    Sd[(idx % W) * kTLd + idx / W] = sv[q];
   }
   // zeros left of the diagonal block (rows cJ .. cJ + ws)
   for (int idx = t; idx < ws * cJ; idx += kTThreads) {
@@ -728,15 +738,32 @@ __global__ __launch_bounds__(kTThreads) void wy_t_level_kernel(int nb, const dou
   double acc[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+  // staged entries are loaded into registers before any LDS write, so each
+  // thread's loads are in flight together
+  constexpr int nBq = W * W / kTThreads, nAq = h * W / kTThreads;
+  static_assert(W * W % kTThreads == 0 && h * W % kTThreads == 0, "staging loops without a tail");
   for (int bb = 0; bb <= tc; ++bb) {
-    __syncthreads();
-    for (int idx = t; idx < W * W; idx += kTThreads) {
-      const int k = idx % W, j = idx / W;
-      Bs[k * kTLd + j] = Tg(c1 + W * bb + k, c1 + W * tc + j);
+    double rb[nBq], ra[nAq];
+#pragma unroll
+    for (int q = 0; q < nBq; ++q) {
+      const int idx = t + q * kTThreads;
+      rb[q] = Tg(c1 + W * bb + idx % W, c1 + W * tc + idx / W);
     }
-    for (int idx = t; idx < h * W; idx += kTThreads) {
-      const int i = idx % h, k = idx / h;
-      As[i * kTLd + k] = Sg(c0 + i, c1 + W * bb + k);
+#pragma unroll
+    for (int q = 0; q < nAq; ++q) {
+      const int idx = t + q * kTThreads;
+      ra[q] = Sg(c0 + idx % h, c1 + W * bb + idx / h);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < nBq; ++q) {
+      const int idx = t + q * kTThreads;
+      Bs[(idx % W) * kTLd + idx / W] = rb[q];
+    }
+#pragma unroll
+    for (int q = 0; q < nAq; ++q) {
+      const int idx = t + q * kTThreads;
+      As[(idx % h) * kTLd + idx / h] = ra[q];
     }
     __syncthreads();
     for (int k = 0; k < W; ++k) {
@@ -751,10 +778,17 @@ __global__ __launch_bounds__(kTThreads) void wy_t_level_kernel(int nb, const dou
   const int rq = t >> 5;
   double o[4] = {0.0, 0.0, 0.0, 0.0};
   for (int a = tr; a < nt; ++a) {
+    double rb[nBq];
+#pragma unroll
+    for (int q = 0; q < nBq; ++q) {
+      const int idx = t + q * kTThreads;
+      rb[q] = Tg(c0 + W * tr + idx % W, c0 + W * a + idx / W);
+    }
     __syncthreads();
-    for (int idx = t; idx < W * W; idx += kTThreads) {
-      const int i = idx % W, k = idx / W;
-      Bs[i * kTLd + k] = Tg(c0 + W * tr + i, c0 + W * a + k);
+#pragma unroll
+    for (int q = 0; q < nBq; ++q) {
+      const int idx = t + q * kTThreads;
+      Bs[(idx % W) * kTLd + idx / W] = rb[q];
     }
     __syncthreads();
     for (int k = 0; k < W; ++k) {
