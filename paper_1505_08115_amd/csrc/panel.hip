@@ -77,9 +77,24 @@ __global__ __launch_bounds__(kPThreads) void panel_qr_kernel(PanelQR p, int rpw,
 
   for (int s = 0; s < nslab && ok; ++s) {
     const int cs = s * W, ws = min(W, nb - cs);
-    for (int idx = t; idx < ws * nrow; idx += kPThreads) {
-      const int c = idx / nrow, r = idx % nrow;
-      X[c * ldx + r] = p.P[(rbeg + r) + (int64_t)(cs + c) * p.ldp];
+    // eight entries per thread are loaded before any is written to LDS, so
+    // the loads are in flight together: a write after each load would wait
+    // for it, one memory latency per entry.  Indices are clamped into the
+    // slab and the writes are unconditional (a load behind a bounds branch is
+    // sunk into it and waits again): past the end, a lane writes the last
+    // entry's own value to it once more.
+    for (int base = 0, tot = ws * nrow; base < tot; base += 8 * kPThreads) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = min(base + t + q * kPThreads, tot - 1), c = idx / nrow, r = idx % nrow;
+        v[q] = p.P[(rbeg + r) + (int64_t)(cs + c) * p.ldp];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = min(base + t + q * kPThreads, tot - 1);
+        X[(idx / nrow) * ldx + idx % nrow] = v[q];
+      }
     }
     // pad rows (nrow .. rpw4) and absent columns (ws .. W) read as zero in the MFMA products
     for (int idx = t; idx < W * (rpw4 - nrow); idx += kPThreads) {
