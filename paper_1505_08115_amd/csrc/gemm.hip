@@ -402,8 +402,27 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t M, int64_t
   const int64_t MN = M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN;
        idx += (int64_t)gridDim.x * blockDim.x) {
+    // the partials are added in split order; eight loads are issued before
+    // their adds so that they are in flight together (a loop of one load and
+    // one add waits a memory latency per split)
     T s = T(0);
-    for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * MN + idx];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(z + u) * MN + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    if (z + 4 <= splits) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = partial[(int64_t)(z + u) * MN + idx];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += v[u];
+      z += 4;
+    }
+    for (; z < splits; ++z) s += partial[(int64_t)z * MN + idx];
     const int64_t i = idx % M, j = idx / M;
     T *cp = C + i + j * ldc;
     *cp = (beta == T(0)) ? alpha * s : alpha * s + beta * (*cp);
