@@ -474,8 +474,18 @@ __global__ __launch_bounds__(256) void gather_moved_kernel(const T *__restrict__
   const int slot = blockIdx.x;
   if (slot >= *moved_cnt) return;
   const int64_t c = r0 + moved[slot];
-  for (int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.y * blockDim.x)
-    tmp[r + slot * m] = A[r + c * lda];
+  // four loads in flight before their stores (a store right after each load
+  // would wait for it)
+  const int64_t stride = (int64_t)gridDim.y * blockDim.x;
+  int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  for (; r + 3 * stride < m; r += 4 * stride) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = A[r + u * stride + c * lda];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tmp[r + u * stride + slot * m] = v[u];
+  }
+  for (; r < m; r += stride) tmp[r + slot * m] = A[r + c * lda];
   if (blockIdx.y == 0 && threadIdx.x == 0) jtmp[slot] = jpvt[c];
 }
 
@@ -490,8 +500,16 @@ __global__ __launch_bounds__(256) void scatter_moved_kernel(T *__restrict__ A, i
   const int slot = blockIdx.x;
   if (slot >= *moved_cnt) return;
   const int64_t d = r0 + dest[moved[slot]];
-  for (int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.y * blockDim.x)
-    A[r + d * lda] = tmp[r + slot * m];
+  const int64_t stride = (int64_t)gridDim.y * blockDim.x;
+  int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  for (; r + 3 * stride < m; r += 4 * stride) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = tmp[r + u * stride + slot * m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) A[r + u * stride + d * lda] = v[u];
+  }
+  for (; r < m; r += stride) A[r + d * lda] = tmp[r + slot * m];
   if (blockIdx.y == 0 && threadIdx.x == 0) jpvt[d] = jtmp[slot];
 }
 
